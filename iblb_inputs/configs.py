@@ -1,0 +1,212 @@
+"""Seeded synthetic workloads shaped like the paper's spreading runs.
+
+A workload is a list of lattice boxes and a list of droplets, each droplet
+living in one box.  The five named workloads reproduce the box sizes, mesh
+resolutions, contact angles, relaxation times and surface tensions of the
+spreading experiments (paper Sec. 3 and Sec. 4: droplets of radius R0 with
+xi/R0 = 0.05, mesh edges of about one lattice unit, a flat wetting wall at the
+bottom, periodic sides) at sizes from a few thousand to 67 million cells.
+
+Only input values are produced here: the wetting amplitude A, the volume V0,
+the node normals and everything else the method computes are left to the
+oracle and to the library.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+from . import mesh as _mesh
+
+Z_WALLS = 0
+Z_PERIODIC = 1
+
+F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
+STORAGE_NAMES = {F64: "f64", F32: "f32", F16DEV: "f16dev", BF16DEV: "bf16dev"}
+
+
+@dataclass
+class Box:
+    nx: int
+    ny: int
+    nz: int
+    tau: float
+    rho0: float = 1.0
+    zbc: int = Z_WALLS
+    body_force: tuple = (0.0, 0.0, 0.0)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+@dataclass
+class Droplet:
+    box: int
+    nodes: np.ndarray          # (N,3) float64, unwrapped coordinates, wall at z = 0
+    tris: np.ndarray           # (T,3) int32, counter-clockwise seen from outside
+    sigma: float
+    theta_eq: float            # rad
+    xi: float
+    n_exp: int = 9
+    m_exp: int = 3
+    k_vol: float = 0.0
+
+
+@dataclass
+class Workload:
+    name: str
+    boxes: list
+    droplets: list
+    steps: int = 1
+    log_every: int = 0
+    storage: int = F32
+    dev_scale: float = 1.0
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def cells(self) -> int:
+        return sum(b.cells for b in self.boxes)
+
+    @property
+    def nodes(self) -> int:
+        return sum(len(d.nodes) for d in self.droplets)
+
+    def with_storage(self, storage: int, dev_scale: float | None = None) -> "Workload":
+        if dev_scale is None:
+            dev_scale = 4096.0 if storage == F16DEV else 1.0
+        return replace(self, storage=storage, dev_scale=dev_scale)
+
+
+def _deg(a: float) -> float:
+    return a * math.pi / 180.0
+
+
+def plain_c1() -> Workload:
+    """32x32x24 box, tau = 1, one level-3 icosphere (642 nodes) of radius 8
+    centred 9 lu above the wetting wall, sigma = 0.01, theta_eq = 90 deg,
+    xi = 0.05 R, no volume penalty, fluid at rest, 200 steps."""
+    r = 8.0
+    v, t = _mesh.sphere(3, r, (16.0, 16.0, 9.0))
+    box = Box(32, 32, 24, tau=1.0)
+    d = Droplet(0, v, t, sigma=0.01, theta_eq=_deg(90.0), xi=0.05 * r, k_vol=0.0)
+    return Workload("plain-fp64-32x32x24-ico3", [box], [d], steps=200, storage=F64)
+
+
+def spreading_c2(steps: int = 20000) -> Workload:
+    """128x128x64 box, tau = 0.8, sigma = 0.005; a level-5 mesh (10242 nodes)
+    holding the volume of a radius-24 sphere, started as a 150 deg cap and
+    relaxing toward theta_eq = 60 deg; h and r_c logged every 100 steps."""
+    r = 24.0
+    xi = 0.05 * r
+    v, t = _mesh.cap_on_wall(5, r, _deg(150.0), 64.0, 64.0, xi)
+    box = Box(128, 128, 64, tau=0.8)
+    sigma = 0.005
+    d = Droplet(0, v, t, sigma=sigma, theta_eq=_deg(60.0), xi=xi, k_vol=2.0 * sigma / r)
+    return Workload("spreading-fp32-128x128x64-ico5", [box], [d], steps=steps,
+                    log_every=100, storage=F32)
+
+
+def precision_c3(tau: float = 0.6, steps: int = 10000) -> Workload:
+    """256x256x128 box, one level-6 sphere (40962 nodes) of radius 48 resting
+    at height xi above the wall, theta_eq = 45 deg, sigma = 0.005."""
+    r = 48.0
+    xi = 0.05 * r
+    v, t = _mesh.sphere_above_wall(6, r, 128.0, 128.0, xi)
+    box = Box(256, 256, 128, tau=tau)
+    sigma = 0.005
+    d = Droplet(0, v, t, sigma=sigma, theta_eq=_deg(45.0), xi=xi, k_vol=2.0 * sigma / r)
+    return Workload(f"precision-256x256x128-ico6-tau{tau:g}", [box], [d], steps=steps,
+                    storage=F32)
+
+
+def batched_c4(seed: int = 17463, n_boxes: int = 64, steps: int = 1000) -> Workload:
+    """64 independent boxes of uneven sizes (48^3 up to 128x128x64), each with
+    one sphere of radius U[10,24] (level 4 below 17, else level 5) resting at
+    height xi, theta_eq U[30,150] deg, tau U[0.6,1.5], sigma = 0.005."""
+    rng = np.random.default_rng(seed)
+    sides = np.arange(48, 129, 16)
+    heights = np.array([48, 56, 64])
+    boxes, drops = [], []
+    sigma = 0.005
+    for b in range(n_boxes):
+        lx = int(rng.choice(sides))
+        ly = int(rng.choice(sides))
+        lz = int(rng.choice(heights))
+        while True:
+            r = float(rng.uniform(10.0, 24.0))
+            xi = 0.05 * r
+            if 2 * r + 8 <= min(lx, ly) and 2 * r + xi + 6 <= lz:
+                break
+        level = 4 if r < 17.0 else 5
+        theta = _deg(float(rng.uniform(30.0, 150.0)))
+        tau = float(rng.uniform(0.6, 1.5))
+        v, t = _mesh.sphere_above_wall(level, r, lx / 2.0, ly / 2.0, xi)
+        boxes.append(Box(lx, ly, lz, tau=tau))
+        drops.append(Droplet(b, v, t, sigma=sigma, theta_eq=theta, xi=xi,
+                             k_vol=2.0 * sigma / r))
+    return Workload(f"batched-{n_boxes}boxes-seed{seed}", boxes, drops, steps=steps,
+                    storage=F32)
+
+
+def multidroplet_c5(seed: int = 17464, steps: int = 5000) -> Workload:
+    """512x512x256 box (67M cells), 16 level-5 spheres on a 4x4 grid of
+    centres (64 + 128 i, 64 + 128 j), radii U[20,32], theta_eq U[40,120] deg,
+    tau = 0.9, sigma = 0.005."""
+    rng = np.random.default_rng(seed)
+    box = Box(512, 512, 256, tau=0.9)
+    drops = []
+    sigma = 0.005
+    for i in range(4):
+        for j in range(4):
+            r = float(rng.uniform(20.0, 32.0))
+            xi = 0.05 * r
+            theta = _deg(float(rng.uniform(40.0, 120.0)))
+            v, t = _mesh.sphere_above_wall(5, r, 64.0 + 128.0 * i, 64.0 + 128.0 * j, xi)
+            drops.append(Droplet(0, v, t, sigma=sigma, theta_eq=theta, xi=xi,
+                                 k_vol=2.0 * sigma / r))
+    return Workload("multidroplet-512x512x256-16xico5", [box], drops, steps=steps,
+                    storage=F32)
+
+
+def poiseuille(nx: int = 4, ny: int = 4, nz: int = 24, tau: float = 0.8,
+               g: float = 1e-6) -> Workload:
+    """Empty channel between the two walls driven by a body force along x."""
+    return Workload(f"poiseuille-{nz}-tau{tau:g}", [Box(nx, ny, nz, tau=tau,
+                    body_force=(g, 0.0, 0.0))], [], storage=F64)
+
+
+def free_droplet(n: int = 32, r: float = 8.0, level: int = 3, tau: float = 1.0,
+                 sigma: float = 0.01) -> Workload:
+    """Droplet in a fully periodic box with no wall interaction (theta = 180
+    deg makes the wetting amplitude vanish)."""
+    v, t = _mesh.sphere(level, r, (n / 2.0, n / 2.0, n / 2.0))
+    box = Box(n, n, n, tau=tau, zbc=Z_PERIODIC)
+    d = Droplet(0, v, t, sigma=sigma, theta_eq=math.pi, xi=0.05 * r, k_vol=0.0)
+    return Workload(f"free-droplet-{n}", [box], [d], storage=F64)
+
+
+def perturbed_populations(box: Box, seed: int, amplitude: float = 1e-3) -> np.ndarray:
+    """Random populations around the rest state, [19][nz][ny][nx] in the order
+    of the velocity set passed later by the caller (weights w): returns a
+    multiplicative noise field eta with f = w * rho0 * (1 + eta)."""
+    rng = np.random.default_rng(seed)
+    return amplitude * rng.standard_normal((19, box.nz, box.ny, box.nx))
+
+
+def jitter_nodes(nodes: np.ndarray, seed: int, amplitude: float) -> np.ndarray:
+    """Nodes moved by a seeded uniform offset in [-amplitude, amplitude]^3."""
+    rng = np.random.default_rng(seed)
+    return nodes + rng.uniform(-amplitude, amplitude, size=nodes.shape)
+
+
+NAMED = {
+    "c1": plain_c1,
+    "c2": spreading_c2,
+    "c3": precision_c3,
+    "c4": batched_c4,
+    "c5": multidroplet_c5,
+}
