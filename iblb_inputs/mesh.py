@@ -11,6 +11,8 @@ Sec. 2 assumes for the outward normal n.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 # The 12 vertices and 20 faces of a regular icosahedron (golden-ratio
@@ -48,12 +50,18 @@ def _orient_outward(v: np.ndarray, f: np.ndarray) -> np.ndarray:
 
 
 def icosphere(level: int) -> tuple[np.ndarray, np.ndarray]:
-    """Unit icosphere after `level` 4:1 subdivisions.
+    """Unit icosphere after `level` 4:1 subdivisions (fresh copies).
 
     Returns (nodes (N,3) float64, tris (T,3) int32) with N = 10*4^L + 2 and
     T = 20*4^L.  New vertices are edge midpoints pushed onto the unit sphere;
     numbering is deterministic (original vertices first, then midpoints in the
     order edges are met while walking the faces)."""
+    v, f = _icosphere_cached(int(level))
+    return v.copy(), f.copy()
+
+
+@functools.lru_cache(maxsize=None)
+def _icosphere_cached(level: int) -> tuple[np.ndarray, np.ndarray]:
     if level < 0:
         raise ValueError("level must be >= 0")
     v = [tuple(p / np.linalg.norm(p)) for p in _ICO_V]

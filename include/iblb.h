@@ -1,0 +1,214 @@
+/*
+ * iblb.h - C ABI of the MI355X (gfx950) immersed boundary - lattice
+ * Boltzmann (IBLB) wetting step.
+ *
+ * The library advances, on one GPU, lattice boxes of D3Q19 BGK fluid with
+ * Guo forcing (paper Sec. 2, Eqs. 1-6) coupled to closed triangulated droplet
+ * meshes through Peskin 4-point interpolation and spreading (Eqs. 7-8), the
+ * droplets carrying surface tension and the wetting interaction
+ * Pi(d) = A[(xi/d)^n - (xi/d)^m] with A from the contact angle (Eqs. 9-11).
+ *
+ * Conventions shared by every call
+ *   - Lattice units, dx = dt = 1, c_s^2 = 1/3.  Cell (i,j,k) of an
+ *     nx x ny x nz box is centred at (i+1/2, j+1/2, k+1/2).  x and y are
+ *     periodic.  In z the box is periodic (IBLB_Z_PERIODIC, test mode) or
+ *     closed by resting no-slip walls on the planes z = 0 (the wetting
+ *     surface) and z = nz (IBLB_Z_WALLS), realised as halfway bounce-back.
+ *   - Mesh node coordinates are unwrapped lattice coordinates; the height
+ *     above the wall used by Pi is the node's z.
+ *   - Every call returns an iblb_status (0 = success, < 0 = error) and
+ *     never throws; iblb_last_error() gives the message of the last failure.
+ *   - Device work is enqueued on the HIP stream given to iblb_init.
+ *     Calls documented as "synchronising" wait for that stream.
+ *   - Host arrays passed in are read during the call and not retained.
+ *   - The device workspace is owned by the caller, must stay allocated and
+ *     untouched until iblb_destroy, and is never freed by the library.
+ *   - The library keeps its own D3Q19 order (iblb_velocity_set); population
+ *     arrays crossing the ABI use it.
+ */
+#ifndef IBLB_H
+#define IBLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t iblb_status;
+enum {
+    IBLB_OK = 0,
+    IBLB_E_INVAL = -1,     /* bad argument or configuration value           */
+    IBLB_E_MESH = -2,      /* mesh open, non-manifold, mis-oriented, or a
+                              node at or below the wall                     */
+    IBLB_E_DEVICE = -3,    /* a HIP call failed                             */
+    IBLB_E_WORKSPACE = -4, /* workspace missing, misaligned or too small    */
+    IBLB_E_UNSTABLE = -5,  /* the device status word reports an instability */
+    IBLB_E_STATE = -6      /* call not valid in the context's current state */
+};
+
+/* Population storage.  F64 and F32 hold the deviation f_i - w_i rho0 in that
+ * precision (an exact shift; arithmetic in the same precision).  F16DEV and
+ * BF16DEV hold s (f_i - w_i rho0) as IEEE binary16 / bfloat16 with a
+ * power-of-two scale s (dev_scale), converted with round-to-nearest-even,
+ * and compute in FP32. */
+enum { IBLB_F64 = 0, IBLB_F32 = 1, IBLB_F16DEV = 2, IBLB_BF16DEV = 3 };
+
+enum { IBLB_Z_WALLS = 0, IBLB_Z_PERIODIC = 1 };
+
+/* iblb_config.flags */
+enum {
+    IBLB_FLAG_GRAPH = 1u,    /* replay each step as a captured hipGraph      */
+    IBLB_FLAG_AUTOTUNE = 2u, /* time the stream-collide launch shapes at init */
+    IBLB_FLAG_FULL_U = 4u    /* write u of every cell each step (testing);
+                                otherwise only cells near a mesh            */
+};
+
+/* Device status bits (sticky; reported by iblb_observables). */
+enum {
+    IBLB_BIT_RHO = 1u,        /* a density was non-finite or <= 0         */
+    IBLB_BIT_MACH = 2u,       /* |u| exceeded the lattice sound speed     */
+    IBLB_BIT_WALL = 4u,       /* a node reached d <= 0 (Pi is singular)   */
+    IBLB_BIT_JUMP = 8u        /* a node moved more than 1 lu in one step  */
+};
+
+typedef struct {
+    int32_t nx, ny, nz; /* cells; nx, ny, nz >= 4 when the box holds a droplet */
+    int32_t zbc;        /* IBLB_Z_WALLS or IBLB_Z_PERIODIC                    */
+    double tau;         /* BGK relaxation time, > 1/2 (Sec. 2, viscosity
+                           mu = rho c_s^2 (tau - 1/2))                         */
+    double rho0;        /* initial (and reference) density, > 0               */
+    double body_force[3]; /* uniform force density added to every cell's F   */
+} iblb_box;
+
+typedef struct {
+    int32_t box;        /* index of the box holding the droplet               */
+    int32_t n_nodes, n_tris;
+    int32_t n_exp, m_exp; /* exponents of Pi, n > m >= 1 (Eq. 10)             */
+    int32_t reserved;
+    const double *nodes;  /* host [n_nodes][3]                                */
+    const int32_t *tris;  /* host [n_tris][3], counter-clockwise from outside */
+    double sigma;         /* surface tension, >= 0                            */
+    double theta_eq;      /* equilibrium contact angle (rad), in [0, pi]       */
+    double xi;            /* regularisation length of Pi, > 0                  */
+    double k_vol;         /* volume-penalty modulus (0 = off; not in the paper) */
+} iblb_droplet;
+
+typedef struct {
+    int32_t n_boxes, n_droplets;
+    const iblb_box *boxes;
+    const iblb_droplet *droplets;
+    int32_t storage;      /* IBLB_F64 .. IBLB_BF16DEV                          */
+    uint32_t flags;       /* IBLB_FLAG_*                                       */
+    double dev_scale;     /* power of two; used by IBLB_F16DEV (e.g. 4096)     */
+} iblb_config;
+
+typedef struct {
+    int64_t step;
+    double volume, area;   /* FP64 sums over the mesh                          */
+    double z_min, z_max;
+    double height;         /* z_max - z_min: highest minus lowest node (Sec. 3) */
+    double contact_radius; /* mean horizontal distance from the area-weighted
+                              centroid of the points where mesh edges cross
+                              z = z_min + xi (0 if none)                        */
+    double theta_app;      /* 2 atan(height / contact_radius)                  */
+    double centroid[3];    /* area-weighted surface centroid                    */
+    int32_t n_crossings;
+    uint32_t status_bits;
+} iblb_obs;
+
+typedef struct {
+    int64_t step;
+    double mass;           /* FP64 sum of all populations                      */
+    double max_u;          /* max over cells of |sum_i c_i f_i| / rho           */
+    uint32_t status_bits;
+    int32_t reserved;
+} iblb_box_obs;
+
+/* D3Q19 velocities c[19][3] and weights w[19] in the library's order. */
+iblb_status iblb_velocity_set(int32_t *c, double *w);
+
+/* Bytes of device workspace the configuration needs (host only, no device
+ * call).  Fails with IBLB_E_INVAL / IBLB_E_MESH on an invalid configuration. */
+iblb_status iblb_workspace_size(const iblb_config *cfg, size_t *bytes);
+
+/* Validate the configuration, lay out the workspace, upload meshes and
+ * tables, set the fluid at rest (f = w rho0) and compute each droplet's
+ * reference volume V0.  `dev_workspace` must be device memory of at least
+ * iblb_workspace_size bytes, 256-byte aligned.  `hip_stream` is a
+ * hipStream_t (NULL = default stream).  Synchronising. */
+iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
+                      void *hip_stream, struct iblb_ctx **out);
+
+/* Enqueue n_steps full time steps t -> t+1 (forces at q^t, spreading, fused
+ * stream-collide, interpolation of u^t at q^t, forward Euler advection).
+ * Asynchronous.  Returns IBLB_E_STATE after an instability was reported. */
+iblb_status iblb_step(struct iblb_ctx *ctx, int64_t n_steps);
+
+/* Observables of the current state (per droplet and per box).  Either
+ * output may be NULL.  Synchronising.  Returns IBLB_E_UNSTABLE (after
+ * filling the outputs) when any status bit is set; that state is sticky. */
+iblb_status iblb_observables(struct iblb_ctx *ctx, iblb_obs *per_droplet, int32_t n_droplets,
+                             iblb_box_obs *per_box, int32_t n_boxes);
+
+/* Populations f_i(x, t) of box `box` at the current time (before the
+ * collision of the next step), FP64, [19][nz][ny][nx] in the library's
+ * velocity order.  `u_out` (may be NULL): [3][nz][ny][nx] velocity with the
+ * half-force correction of the last step, NaN where it was not written.
+ * Synchronising. */
+iblb_status iblb_read_state(struct iblb_ctx *ctx, int32_t box, double *f_out, double *u_out);
+
+/* Replace the populations of box `box` by f_in (layout as iblb_read_state),
+ * converted to the storage precision.  Synchronising. */
+iblb_status iblb_write_state(struct iblb_ctx *ctx, int32_t box, const double *f_in);
+
+/* Node positions of droplet `d`, [n_nodes][3] in the caller's node order. */
+iblb_status iblb_read_nodes(struct iblb_ctx *ctx, int32_t d, double *nodes_out);
+iblb_status iblb_write_nodes(struct iblb_ctx *ctx, int32_t d, const double *nodes_in);
+
+/* Inspection calls used by parity tests.  Each runs the same kernels as a
+ * step on the current state and copies one intermediate out:
+ *   compute_forces : nodal forces phi_j (Eqs. 9-11), [n_nodes][3]
+ *   compute_spread : spread force density F (Eq. 8) of box b,
+ *                    [3][nz][ny][nx], zero away from the meshes; and the
+ *                    flags of the 4x4x4 tiles holding a stencil cell,
+ *                    [ceil(nz/4)][ceil(ny/4)][ceil(nx/4)] (may be NULL)
+ *   interpolate    : U_j = sum_x u(x) Delta(q_j - x) (Eq. 7) of a given
+ *                    [3][nz][ny][nx] field u, without moving the nodes
+ *   read_bins      : base cell floor(q - 1/2) per axis, x and y wrapped
+ *                    into the box, [n_nodes][3]
+ *   read_csr       : node -> incident triangles, entries 3*t + corner
+ *                    sorted by t; offsets [n_nodes + 1], entries [3 n_tris]
+ * None of them advances time.  Synchronising. */
+iblb_status iblb_compute_forces(struct iblb_ctx *ctx, int32_t d, double *phi_out);
+iblb_status iblb_compute_spread(struct iblb_ctx *ctx, int32_t b, double *F_out,
+                                uint8_t *tile_flags_out);
+iblb_status iblb_interpolate(struct iblb_ctx *ctx, int32_t d, const double *u_in,
+                             double *U_out);
+iblb_status iblb_read_bins(struct iblb_ctx *ctx, int32_t d, int32_t *base_out);
+iblb_status iblb_read_csr(struct iblb_ctx *ctx, int32_t d, int32_t *offsets, int32_t *entries);
+
+/* Launch shape of the fused stream-collide kernel: threads along x per row
+ * (64..1024, multiple of 64, times rows_per_group <= 1024) and rows handled
+ * by one workgroup.  Rebuilds the step graphs.  Synchronising. */
+iblb_status iblb_set_launch(struct iblb_ctx *ctx, int32_t threads_x, int32_t rows_per_group);
+iblb_status iblb_get_launch(const struct iblb_ctx *ctx, int32_t *threads_x,
+                            int32_t *rows_per_group);
+
+/* Average device time (ms) of one stream-collide launch over `reps` launches,
+ * measured with HIP events on the context's stream (the populations are
+ * advanced; the mesh is not).  Synchronising. */
+iblb_status iblb_time_stream_collide(struct iblb_ctx *ctx, int32_t reps, double *ms_out);
+
+/* Free host-side state and graphs (not the caller's workspace). */
+iblb_status iblb_destroy(struct iblb_ctx *ctx);
+
+/* Message of the last error on ctx (or of the last context-less failure when
+ * ctx is NULL).  Never NULL. */
+const char *iblb_last_error(const struct iblb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBLB_H */

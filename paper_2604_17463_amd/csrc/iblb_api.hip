@@ -1,0 +1,1104 @@
+// Host side of the C ABI declared in include/iblb.h: validation, workspace
+// layout, mesh preparation (node renumbering, node -> triangle CSR), uploads,
+// step enqueueing and hipGraph replay, observables and state I/O.
+#include "iblb.h"
+#include "iblb_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+using namespace iblb;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+constexpr size_t ALIGN = 256;
+constexpr size_t BIG_ALIGN = 2u << 20;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int elem_bytes(int storage) { return storage == IBLB_F64 ? 8 : (storage == IBLB_F32 ? 4 : 2); }
+
+struct DropHost {
+    iblb_droplet d{};
+    std::vector<int32_t> perm;  // internal node k -> caller's node id
+    std::vector<int32_t> inv;   // caller's node id -> internal node k
+    std::vector<double> nodes;  // caller's order, copy of the input
+    std::vector<int32_t> tris;  // caller's triangles (caller's node ids)
+    int node_off = 0, blk_off = 0, n_blocks = 0, tri_off = 0, chunk_off = 0, n_chunks = 0;
+    double A = 0.0, ref[3] = {0, 0, 0};
+};
+
+struct BoxHost {
+    iblb_box b{};
+    int sx = 0, tnx = 0, tny = 0, tnz = 0, n_tiles = 0, tile_base = 0;
+    int64_t plane = 0;
+    int blk_begin = 0, blk_end = 0;
+    size_t off_f[2] = {0, 0}, off_stamp = 0, off_F = 0, off_u = 0;
+};
+
+struct Plan {
+    int storage = IBLB_F32;
+    uint32_t flags = 0;
+    double scale = 1.0;
+    int real = 4;  // bytes of the compute type
+    std::vector<BoxHost> boxes;
+    std::vector<DropHost> drops;
+    int Ntot = 0, nblk = 0, Ttot = 0, n_chunks = 0, total_tiles = 0, max_rows = 0;
+    bool any_kvol = false;
+    // workspace offsets
+    size_t off_boxes = 0, off_drops = 0, off_qh = 0, off_ql = 0, off_phi = 0, off_wgt = 0,
+           off_base = 0, off_s0 = 0, off_bbox = 0, off_blk_drop = 0, off_tri = 0,
+           off_csr_off = 0, off_csr_ent = 0, off_chunks = 0, off_tri_part = 0, off_rows = 0,
+           off_tchunk = 0, off_ctr = 0, off_status = 0, off_obs_part = 0, off_obs_out = 0,
+           off_uout = 0, total = 0;
+};
+
+bool finite(double v) { return std::isfinite(v); }
+
+iblb_status fail(std::string *err, iblb_status code, const std::string &msg) {
+    if (err) *err = msg;
+    return code;
+}
+
+// Closed, manifold, consistently oriented: every directed edge once and its
+// reverse once; no repeated corner; every node used.
+iblb_status check_mesh(const iblb_droplet &d, int di, std::string *err) {
+    const int N = d.n_nodes, T = d.n_tris;
+    std::unordered_map<uint64_t, int> edges;
+    edges.reserve((size_t)T * 3 * 2);
+    std::vector<char> used(N, 0);
+    for (int t = 0; t < T; ++t) {
+        const int32_t *c = d.tris + 3 * t;
+        for (int k = 0; k < 3; ++k)
+            if (c[k] < 0 || c[k] >= N)
+                return fail(err, IBLB_E_MESH, "droplet " + std::to_string(di) + ": triangle " +
+                                                  std::to_string(t) + " has a node index out of range");
+        if (c[0] == c[1] || c[1] == c[2] || c[0] == c[2])
+            return fail(err, IBLB_E_MESH, "droplet " + std::to_string(di) + ": degenerate triangle " +
+                                              std::to_string(t));
+        for (int k = 0; k < 3; ++k) {
+            used[c[k]] = 1;
+            const uint64_t key = ((uint64_t)(uint32_t)c[k] << 32) | (uint32_t)c[(k + 1) % 3];
+            if (++edges[key] != 1)
+                return fail(err, IBLB_E_MESH, "droplet " + std::to_string(di) +
+                                                  ": a directed edge occurs twice (non-manifold or "
+                                                  "inconsistently oriented mesh)");
+        }
+    }
+    for (const auto &e : edges) {
+        const uint64_t rev = (e.first << 32) | (e.first >> 32);
+        if (!edges.count(rev))
+            return fail(err, IBLB_E_MESH, "droplet " + std::to_string(di) + ": mesh is not closed");
+    }
+    for (int j = 0; j < N; ++j)
+        if (!used[j])
+            return fail(err, IBLB_E_MESH, "droplet " + std::to_string(di) + ": node " +
+                                              std::to_string(j) + " belongs to no triangle");
+    // orientation: the enclosed volume must be positive (outward normals)
+    double V = 0.0;
+    for (int t = 0; t < T; ++t) {
+        const double *a = d.nodes + 3 * d.tris[3 * t], *b = d.nodes + 3 * d.tris[3 * t + 1],
+                     *c = d.nodes + 3 * d.tris[3 * t + 2];
+        const double bc[3] = {b[1] * c[2] - b[2] * c[1], b[2] * c[0] - b[0] * c[2],
+                              b[0] * c[1] - b[1] * c[0]};
+        V += a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2];
+    }
+    if (!(V > 0))
+        return fail(err, IBLB_E_MESH, "droplet " + std::to_string(di) +
+                                          ": triangles are not counter-clockwise seen from outside");
+    return IBLB_OK;
+}
+
+uint64_t spread3(uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
+    if (!cfg) return fail(err, IBLB_E_INVAL, "config is NULL");
+    if (cfg->n_boxes < 1 || !cfg->boxes) return fail(err, IBLB_E_INVAL, "need at least one box");
+    if (cfg->n_droplets < 0 || (cfg->n_droplets > 0 && !cfg->droplets))
+        return fail(err, IBLB_E_INVAL, "droplet array missing");
+    if (cfg->storage < IBLB_F64 || cfg->storage > IBLB_BF16DEV)
+        return fail(err, IBLB_E_INVAL, "unknown storage");
+    if (cfg->flags & ~(uint32_t)(IBLB_FLAG_GRAPH | IBLB_FLAG_AUTOTUNE | IBLB_FLAG_FULL_U))
+        return fail(err, IBLB_E_INVAL, "unknown flag bits");
+    p.storage = cfg->storage;
+    p.flags = cfg->flags;
+    p.real = cfg->storage == IBLB_F64 ? 8 : 4;
+    p.scale = 1.0;
+    if (cfg->storage == IBLB_F16DEV) {
+        int e = 0;
+        const double m = std::frexp(cfg->dev_scale, &e);
+        if (!(cfg->dev_scale > 0) || !finite(cfg->dev_scale) || m != 0.5 || cfg->dev_scale > 65536.0)
+            return fail(err, IBLB_E_INVAL, "dev_scale must be a power of two in (0, 65536]");
+        p.scale = cfg->dev_scale;
+    }
+    const int eb = elem_bytes(cfg->storage);
+    p.boxes.resize(cfg->n_boxes);
+    for (int b = 0; b < cfg->n_boxes; ++b) {
+        const iblb_box &B = cfg->boxes[b];
+        const std::string nm = "box " + std::to_string(b);
+        if (B.nx < 1 || B.ny < 1 || B.nz < 1) return fail(err, IBLB_E_INVAL, nm + ": sizes must be >= 1");
+        if (B.zbc != IBLB_Z_WALLS && B.zbc != IBLB_Z_PERIODIC)
+            return fail(err, IBLB_E_INVAL, nm + ": unknown z boundary");
+        if (!(B.tau > 0.5) || !finite(B.tau)) return fail(err, IBLB_E_INVAL, nm + ": tau must exceed 1/2");
+        if (!(B.rho0 > 0) || !finite(B.rho0)) return fail(err, IBLB_E_INVAL, nm + ": rho0 must be > 0");
+        for (int a = 0; a < 3; ++a)
+            if (!finite(B.body_force[a])) return fail(err, IBLB_E_INVAL, nm + ": body force not finite");
+        BoxHost &H = p.boxes[b];
+        H.b = B;
+        H.sx = (int)round_up((size_t)B.nx, 128 / eb);
+        H.plane = (int64_t)round_up((size_t)H.sx * B.ny * B.nz, 64);
+        if ((int64_t)B.ny * B.nz >= (1LL << 31) || H.plane * eb >= (1LL << 40))
+            return fail(err, IBLB_E_INVAL, nm + ": box too large");
+        H.tnx = (B.nx + 3) / 4;
+        H.tny = (B.ny + 3) / 4;
+        H.tnz = (B.nz + 3) / 4;
+        H.n_tiles = H.tnx * H.tny * H.tnz;
+        H.tile_base = p.total_tiles;
+        p.total_tiles += (int)round_up((size_t)H.n_tiles, TILE_CELLS);
+        p.max_rows += B.ny * B.nz;
+    }
+    p.drops.resize(cfg->n_droplets);
+    // droplets are laid out box by box so each box owns a contiguous block range
+    std::vector<int> order(cfg->n_droplets);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return cfg->droplets[a].box < cfg->droplets[b].box; });
+    for (int di = 0; di < cfg->n_droplets; ++di) {
+        const iblb_droplet &D = cfg->droplets[di];
+        const std::string nm = "droplet " + std::to_string(di);
+        if (D.box < 0 || D.box >= cfg->n_boxes) return fail(err, IBLB_E_INVAL, nm + ": bad box index");
+        if (D.n_nodes < 4 || D.n_tris < 4 || !D.nodes || !D.tris)
+            return fail(err, IBLB_E_INVAL, nm + ": mesh arrays missing or too small");
+        if (!(D.sigma >= 0) || !finite(D.sigma)) return fail(err, IBLB_E_INVAL, nm + ": sigma must be >= 0");
+        if (!(D.theta_eq >= 0 && D.theta_eq <= M_PI))
+            return fail(err, IBLB_E_INVAL, nm + ": theta_eq must lie in [0, pi]");
+        if (!(D.xi > 0) || !finite(D.xi)) return fail(err, IBLB_E_INVAL, nm + ": xi must be > 0");
+        if (!(D.n_exp > D.m_exp && D.m_exp >= 1 && D.n_exp <= 64))
+            return fail(err, IBLB_E_INVAL, nm + ": need 64 >= n > m >= 1");
+        if (!(D.k_vol >= 0) || !finite(D.k_vol)) return fail(err, IBLB_E_INVAL, nm + ": k_vol must be >= 0");
+        const iblb_box &B = cfg->boxes[D.box];
+        if (B.nx < 4 || B.ny < 4 || B.nz < 4)
+            return fail(err, IBLB_E_INVAL, nm + ": a box holding a droplet needs nx, ny, nz >= 4");
+        for (int k = 0; k < 3 * D.n_nodes; ++k)
+            if (!finite(D.nodes[k])) return fail(err, IBLB_E_INVAL, nm + ": node coordinate not finite");
+        iblb_status st = check_mesh(D, di, err);
+        if (st != IBLB_OK) return st;
+        if (B.zbc == IBLB_Z_WALLS) {
+            for (int j = 0; j < D.n_nodes; ++j)
+                if (!(D.nodes[3 * j + 2] > 0.0) || !(D.nodes[3 * j + 2] < B.nz))
+                    return fail(err, IBLB_E_MESH, nm + ": node " + std::to_string(j) +
+                                                      " is not strictly between the walls");
+        }
+    }
+    int blk = 0, tri = 0, chunk = 0;
+    for (int oi = 0; oi < cfg->n_droplets; ++oi) {
+        const int di = order[oi];
+        const iblb_droplet &D = cfg->droplets[di];
+        DropHost &H = p.drops[di];
+        H.d = D;
+        H.nodes.assign(D.nodes, D.nodes + 3 * (size_t)D.n_nodes);
+        H.tris.assign(D.tris, D.tris + 3 * (size_t)D.n_tris);
+        H.d.nodes = nullptr;
+        H.d.tris = nullptr;
+        H.n_blocks = (D.n_nodes + NB - 1) / NB;
+        H.blk_off = blk;
+        H.node_off = blk * NB;
+        blk += H.n_blocks;
+        H.tri_off = tri;
+        tri += D.n_tris;
+        H.n_chunks = (D.n_tris + TRI_CHUNK - 1) / TRI_CHUNK;
+        H.chunk_off = chunk;
+        chunk += H.n_chunks;
+        H.A = D.sigma * (double)((D.m_exp - 1) * (D.n_exp - 1)) / ((double)(D.n_exp - D.m_exp) * D.xi) *
+              (1.0 + std::cos(D.theta_eq));  // Eq. 11
+        if (D.k_vol > 0) p.any_kvol = true;
+        // Morton order of the initial positions (1 lu cells) for compact node blocks
+        double mn[3] = {1e300, 1e300, 1e300};
+        for (int j = 0; j < D.n_nodes; ++j)
+            for (int a = 0; a < 3; ++a) mn[a] = std::min(mn[a], D.nodes[3 * j + a]);
+        std::vector<uint64_t> key(D.n_nodes);
+        for (int j = 0; j < D.n_nodes; ++j) {
+            uint64_t k = 0;
+            for (int a = 0; a < 3; ++a)
+                k |= spread3((uint64_t)std::floor(D.nodes[3 * j + a] - mn[a])) << a;
+            key[j] = k;
+        }
+        H.perm.resize(D.n_nodes);
+        std::iota(H.perm.begin(), H.perm.end(), 0);
+        std::stable_sort(H.perm.begin(), H.perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+        H.inv.resize(D.n_nodes);
+        for (int k = 0; k < D.n_nodes; ++k) H.inv[H.perm[k]] = k;
+        double c[3] = {0, 0, 0};
+        for (int j = 0; j < D.n_nodes; ++j)
+            for (int a = 0; a < 3; ++a) c[a] += D.nodes[3 * j + a];
+        for (int a = 0; a < 3; ++a) H.ref[a] = std::floor(c[a] / D.n_nodes);
+    }
+    p.nblk = blk;
+    p.Ntot = blk * NB;
+    p.Ttot = tri;
+    p.n_chunks = chunk;
+    for (int b = 0; b < cfg->n_boxes; ++b) {
+        BoxHost &H = p.boxes[b];
+        H.blk_begin = H.blk_end = 0;
+        bool any = false;
+        for (const auto &dh : p.drops)
+            if (dh.d.box == b) {
+                if (!any) H.blk_begin = dh.blk_off;
+                any = true;
+                H.blk_end = std::max(H.blk_end, dh.blk_off + dh.n_blocks);
+            }
+    }
+
+    // workspace layout
+    size_t o = 0;
+    auto take = [&](size_t bytes, size_t al = ALIGN) {
+        o = round_up(o, al);
+        const size_t r = o;
+        o += std::max<size_t>(bytes, 1);
+        return r;
+    };
+    for (auto &H : p.boxes) {
+        for (int k = 0; k < 2; ++k) H.off_f[k] = take((size_t)Q * H.plane * eb, BIG_ALIGN);
+        H.off_stamp = take((size_t)H.n_tiles * 4);
+        H.off_F = take((size_t)H.n_tiles * 3 * TILE_CELLS * p.real);
+        H.off_u = take((size_t)H.n_tiles * 3 * TILE_CELLS * p.real);
+    }
+    p.off_boxes = take(sizeof(BoxDev) * p.boxes.size());
+    p.off_drops = take(sizeof(DropDev) * std::max<size_t>(p.drops.size(), 1));
+    const size_t N = (size_t)p.Ntot;
+    p.off_qh = take(3 * N * p.real);
+    p.off_ql = take(3 * N * p.real);
+    p.off_phi = take(3 * N * p.real);
+    p.off_wgt = take(12 * N * p.real);
+    p.off_base = take(3 * N * 4);
+    p.off_s0 = take(3 * N * 4);
+    p.off_bbox = take(6 * (size_t)p.nblk * 4);
+    p.off_blk_drop = take((size_t)p.nblk * 4);
+    p.off_tri = take(3 * (size_t)p.Ttot * 4);
+    p.off_csr_off = take((N + 1) * 4);
+    p.off_csr_ent = take(3 * (size_t)p.Ttot * 4);
+    p.off_chunks = take(sizeof(TriChunk) * (size_t)p.n_chunks);
+    p.off_tri_part = take(2 * (size_t)p.n_chunks * 8);
+    p.off_rows = take(sizeof(RowGroup) * (size_t)p.max_rows);
+    p.off_tchunk = take((size_t)(p.total_tiles / TILE_CELLS) * 4);
+    p.off_ctr = take(4);
+    p.off_status = take(4);
+    p.off_obs_part = take(2 * (size_t)OBS_GROUPS * 8);
+    p.off_obs_out = take(((size_t)p.drops.size() * OBS_DROP + p.boxes.size() * OBS_BOX) * 8);
+    p.off_uout = take(3 * N * 8);
+    p.total = round_up(o, ALIGN);
+    return IBLB_OK;
+}
+
+}  // namespace
+
+struct iblb_ctx {
+    Plan plan;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;
+    DevPtrs P{};
+    Launch L{};
+    int rows_per_group = 1;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int parity = 0;
+    int64_t step = 0;
+    int32_t epoch = 0;       // host mirror of the device step epoch
+    int32_t last_step_epoch = -1;
+    bool unstable = false;
+    std::string err = "no error";
+    double *host_obs = nullptr;
+    uint32_t *host_status = nullptr;
+};
+
+namespace {
+
+iblb_status set_err(iblb_ctx *c, iblb_status code, const std::string &msg) {
+    if (c) c->err = msg;
+    g_last_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return set_err(ctx, IBLB_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_f64(const iblb_ctx *c) { return c->plan.storage == IBLB_F64; }
+
+iblb_status upload_rows(iblb_ctx *c) {
+    std::vector<RowGroup> rows;
+    const int R = c->rows_per_group;
+    for (int b = 0; b < (int)c->plan.boxes.size(); ++b) {
+        const int nr = c->plan.boxes[b].b.ny * c->plan.boxes[b].b.nz;
+        for (int r = 0; r < nr; r += R) rows.push_back({b, r, std::min(r + R, nr), 0});
+    }
+    c->P.n_rowgroups = (int)rows.size();
+    c->L.grid = (int)rows.size();
+    HIPCHK(c, hipMemcpyAsync(c->P.rows, rows.data(), rows.size() * sizeof(RowGroup),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return IBLB_OK;
+}
+
+iblb_status enqueue_step(iblb_ctx *c, hipStream_t s, int parity) {
+    const bool f64 = is_f64(c);
+    if (c->plan.any_kvol) HIPCHK(c, launch_tri_sums(c->P, f64, s));
+    HIPCHK(c, launch_node(c->P, f64, 0, s));
+    HIPCHK(c, launch_spread(c->P, f64, s));
+    HIPCHK(c, launch_stream_collide(c->P, c->plan.storage, parity,
+                                    (c->plan.flags & IBLB_FLAG_FULL_U) ? 1 : 0, (float)c->plan.scale,
+                                    c->L, s));
+    HIPCHK(c, launch_interp(c->P, f64, 0, nullptr, s));
+    return IBLB_OK;
+}
+
+void drop_graphs(iblb_ctx *c) {
+    for (auto &e : c->exec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+}
+
+iblb_status build_graphs(iblb_ctx *c) {
+    drop_graphs(c);
+    if (!(c->plan.flags & IBLB_FLAG_GRAPH)) return IBLB_OK;
+    if (!c->capture) HIPCHK(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+    for (int p = 0; p < 2; ++p) {
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+        iblb_status st = enqueue_step(c, c->capture, p);
+        hipError_t e = hipStreamEndCapture(c->capture, &g);
+        if (st != IBLB_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return set_err(c, IBLB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->exec[p], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return set_err(c, IBLB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return IBLB_OK;
+}
+
+iblb_status check_launch(iblb_ctx *c, int bx, int by) {
+    if (bx < 32 || bx > 1024 || (bx & 31) || by < 1 || bx * by > 1024 || (bx * by) % 64)
+        return set_err(c, IBLB_E_INVAL, "launch shape: threads_x in [32,1024] multiple of 32, "
+                                        "threads_x*rows a multiple of 64 and <= 1024");
+    return IBLB_OK;
+}
+
+iblb_status time_k1(iblb_ctx *c, int reps, double *ms) {
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    HIPCHK(c, hipEventRecord(a, c->stream));
+    for (int r = 0; r < reps; ++r) {
+        HIPCHK(c, launch_stream_collide(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, c->L,
+                                        c->stream));
+        c->parity ^= 1;
+    }
+    HIPCHK(c, hipEventRecord(b, c->stream));
+    HIPCHK(c, hipEventSynchronize(b));
+    float t = 0;
+    HIPCHK(c, hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = (double)t / reps;
+    return IBLB_OK;
+}
+
+iblb_status autotune(iblb_ctx *c) {
+    int nxmax = 0;
+    for (auto &H : c->plan.boxes) nxmax = std::max(nxmax, H.b.nx);
+    const int saved_parity = c->parity;
+    double best = 1e300;
+    int bbx = c->L.bx, bby = c->L.by;
+    for (int bx : {32, 64, 128, 256, 512}) {
+        if (bx > (int)round_up((size_t)nxmax, 32)) continue;
+        for (int threads : {256, 512}) {
+            const int by = threads / bx;
+            if (by < 1 || check_launch(c, bx, by) != IBLB_OK) continue;
+            c->L.bx = bx;
+            c->L.by = by;
+            c->rows_per_group = by;
+            iblb_status st = upload_rows(c);
+            if (st != IBLB_OK) return st;
+            double ms = 0;
+            st = time_k1(c, 3, &ms);
+            if (st == IBLB_OK) st = time_k1(c, 10, &ms);
+            if (st != IBLB_OK) return st;
+            if (ms < best) {
+                best = ms;
+                bbx = bx;
+                bby = by;
+            }
+        }
+    }
+    c->L.bx = bbx;
+    c->L.by = bby;
+    c->rows_per_group = bby;
+    iblb_status st = upload_rows(c);
+    if (st != IBLB_OK) return st;
+    // the timing runs advanced the fluid without the meshes: back to rest
+    c->parity = saved_parity;
+    for (auto &H : c->plan.boxes)
+        for (int k = 0; k < 2; ++k)
+            HIPCHK(c, hipMemsetAsync(c->ws + H.off_f[k], 0,
+                                     (size_t)Q * H.plane * elem_bytes(c->plan.storage), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return IBLB_OK;
+}
+
+// ---- host conversion of stored populations (I/O only) ----
+double decode(const iblb_ctx *c, const void *raw, size_t i) {
+    switch (c->plan.storage) {
+    case IBLB_F64: return ((const double *)raw)[i];
+    case IBLB_F32: return ((const float *)raw)[i];
+    case IBLB_F16DEV: return (double)(float)((const _Float16 *)raw)[i] / c->plan.scale;
+    default: {
+        uint32_t bits = (uint32_t)((const uint16_t *)raw)[i] << 16;
+        float f;
+        std::memcpy(&f, &bits, 4);
+        return f;
+    }
+    }
+}
+
+void encode(const iblb_ctx *c, void *raw, size_t i, double v) {
+    switch (c->plan.storage) {
+    case IBLB_F64: ((double *)raw)[i] = v; break;
+    case IBLB_F32: ((float *)raw)[i] = (float)v; break;
+    case IBLB_F16DEV: ((_Float16 *)raw)[i] = (_Float16)(float)(v * c->plan.scale); break;
+    default: {
+        const float f = (float)v;
+        uint32_t bits;
+        std::memcpy(&bits, &f, 4);
+        bits += 0x7fffu + ((bits >> 16) & 1u);  // round to nearest even
+        ((uint16_t *)raw)[i] = (uint16_t)(bits >> 16);
+    }
+    }
+}
+
+inline int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+}  // namespace
+
+// =====================================================================  ABI
+
+extern "C" {
+
+iblb_status iblb_velocity_set(int32_t *c, double *w) {
+    if (!c || !w) return set_err(nullptr, IBLB_E_INVAL, "NULL output");
+    for (int i = 0; i < Q; ++i) {
+        c[3 * i] = cx_of(i);
+        c[3 * i + 1] = cy_of(i);
+        c[3 * i + 2] = cz_of(i);
+        w[i] = w_of(i);
+    }
+    return IBLB_OK;
+}
+
+iblb_status iblb_workspace_size(const iblb_config *cfg, size_t *bytes) {
+    if (!bytes) return set_err(nullptr, IBLB_E_INVAL, "bytes is NULL");
+    Plan p;
+    std::string err;
+    iblb_status st = build_plan(cfg, p, &err);
+    if (st != IBLB_OK) return set_err(nullptr, st, err);
+    *bytes = p.total;
+    return IBLB_OK;
+}
+
+iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
+                      iblb_ctx **out) {
+    if (!out) return set_err(nullptr, IBLB_E_INVAL, "out is NULL");
+    *out = nullptr;
+    iblb_ctx *c = new iblb_ctx();
+    std::string err;
+    iblb_status st = build_plan(cfg, c->plan, &err);
+    if (st != IBLB_OK) {
+        delete c;
+        return set_err(nullptr, st, err);
+    }
+    Plan &p = c->plan;
+    if (!dev_workspace || ((uintptr_t)dev_workspace % ALIGN) != 0 || bytes < p.total) {
+        delete c;
+        return set_err(nullptr, IBLB_E_WORKSPACE,
+                       "workspace must be 256-byte aligned device memory of at least " +
+                           std::to_string(p.total) + " bytes");
+    }
+    c->ws = (char *)dev_workspace;
+    c->stream = (hipStream_t)hip_stream;
+    auto at = [&](size_t off) { return (void *)(c->ws + off); };
+    DevPtrs &P = c->P;
+    P.boxes = (BoxDev *)at(p.off_boxes);
+    P.drops = (DropDev *)at(p.off_drops);
+    P.n_boxes = (int)p.boxes.size();
+    P.n_drops = (int)p.drops.size();
+    P.qh = at(p.off_qh);
+    P.ql = at(p.off_ql);
+    P.phi = at(p.off_phi);
+    P.wgt = at(p.off_wgt);
+    P.base = (int32_t *)at(p.off_base);
+    P.s0 = (int32_t *)at(p.off_s0);
+    P.bbox = (int32_t *)at(p.off_bbox);
+    P.blk_drop = (int32_t *)at(p.off_blk_drop);
+    P.tri = (int32_t *)at(p.off_tri);
+    P.csr_off = (int32_t *)at(p.off_csr_off);
+    P.csr_ent = (int32_t *)at(p.off_csr_ent);
+    P.chunks = (TriChunk *)at(p.off_chunks);
+    P.tri_part = (double *)at(p.off_tri_part);
+    P.rows = (RowGroup *)at(p.off_rows);
+    P.tchunk_box = (int32_t *)at(p.off_tchunk);
+    P.ctr = (int32_t *)at(p.off_ctr);
+    P.status = (uint32_t *)at(p.off_status);
+    P.obs_part = (double *)at(p.off_obs_part);
+    P.obs_out = (double *)at(p.off_obs_out);
+    P.Ntot = p.Ntot;
+    P.nblk = p.nblk;
+    P.Ttot = p.Ttot;
+    P.n_chunks = p.n_chunks;
+    P.total_tiles = p.total_tiles;
+    P.obs_groups = OBS_GROUPS;
+
+    // host tables
+    std::vector<BoxDev> bd(p.boxes.size());
+    std::vector<int32_t> tchunk(p.total_tiles / TILE_CELLS, 0);
+    for (size_t b = 0; b < p.boxes.size(); ++b) {
+        const BoxHost &H = p.boxes[b];
+        BoxDev &D = bd[b];
+        D.nx = H.b.nx;
+        D.ny = H.b.ny;
+        D.nz = H.b.nz;
+        D.zbc = H.b.zbc;
+        D.sx = H.sx;
+        D.tnx = H.tnx;
+        D.tny = H.tny;
+        D.tnz = H.tnz;
+        D.plane = H.plane;
+        D.n_tiles = H.n_tiles;
+        D.tile_base = H.tile_base;
+        D.blk_begin = H.blk_begin;
+        D.blk_end = H.blk_end;
+        D.f[0] = at(H.off_f[0]);
+        D.f[1] = at(H.off_f[1]);
+        D.Fband = at(H.off_F);
+        D.uband = at(H.off_u);
+        D.stamp = (int32_t *)at(H.off_stamp);
+        D.tau = H.b.tau;
+        D.rho0 = H.b.rho0;
+        for (int a = 0; a < 3; ++a) D.g[a] = H.b.body_force[a];
+        D.omega = 1.0 / H.b.tau;
+        D.guo = 1.0 - 1.0 / (2.0 * H.b.tau);
+        D.cells_rho0 = (double)H.b.nx * H.b.ny * H.b.nz * H.b.rho0;
+        for (int k = 0; k < (int)round_up((size_t)H.n_tiles, TILE_CELLS) / TILE_CELLS; ++k)
+            tchunk[H.tile_base / TILE_CELLS + k] = (int32_t)b;
+    }
+    const int N = p.Ntot;
+    const int R = p.real;
+    std::vector<char> qh((size_t)3 * N * R, 0), ql((size_t)3 * N * R, 0);
+    std::vector<int32_t> tri((size_t)3 * std::max(p.Ttot, 1)), csr_off((size_t)N + 1, 0),
+        csr_ent((size_t)3 * std::max(p.Ttot, 1)), blk_drop(std::max(p.nblk, 1));
+    std::vector<TriChunk> chunks(std::max(p.n_chunks, 1));
+    std::vector<DropDev> dd(std::max<size_t>(p.drops.size(), 1));
+    for (size_t di = 0; di < p.drops.size(); ++di) {
+        const DropHost &H = p.drops[di];
+        DropDev &D = dd[di];
+        D.box = H.d.box;
+        D.n_nodes = H.d.n_nodes;
+        D.n_tris = H.d.n_tris;
+        D.n_exp = H.d.n_exp;
+        D.m_exp = H.d.m_exp;
+        D.node_off = H.node_off;
+        D.blk_off = H.blk_off;
+        D.n_blocks = H.n_blocks;
+        D.tri_off = H.tri_off;
+        D.chunk_off = H.chunk_off;
+        D.n_chunks = H.n_chunks;
+        D.sigma = H.d.sigma;
+        D.A = H.A;
+        D.xi = H.d.xi;
+        D.kvol = H.d.k_vol;
+        D.V0 = 0.0;
+        for (int a = 0; a < 3; ++a) D.ref[a] = H.ref[a];
+        for (int k = 0; k < H.n_blocks; ++k) blk_drop[H.blk_off + k] = (int32_t)di;
+        for (int k = 0; k < H.n_chunks; ++k) {
+            const int t0 = H.tri_off + k * TRI_CHUNK;
+            chunks[H.chunk_off + k] = {(int32_t)di, t0, std::min(t0 + TRI_CHUNK, H.tri_off + H.d.n_tris), 0};
+        }
+        for (int k = 0; k < H.d.n_nodes; ++k) {
+            const int j = H.node_off + k;
+            for (int a = 0; a < 3; ++a) {
+                const double v = H.nodes[3 * H.perm[k] + a];
+                if (R == 8) {
+                    ((double *)qh.data())[(size_t)a * N + j] = v;
+                } else {
+                    const float h = (float)v;
+                    ((float *)qh.data())[(size_t)a * N + j] = h;
+                    ((float *)ql.data())[(size_t)a * N + j] = (float)(v - (double)h);
+                }
+            }
+        }
+        for (int t = 0; t < H.d.n_tris; ++t)
+            for (int cc = 0; cc < 3; ++cc)
+                tri[3 * (size_t)(H.tri_off + t) + cc] = H.node_off + H.inv[H.tris[3 * t + cc]];
+    }
+    // node -> incident triangles, ascending triangle id
+    for (int t = 0; t < p.Ttot; ++t)
+        for (int cc = 0; cc < 3; ++cc) csr_off[tri[3 * t + cc] + 1] += 1;
+    for (int j = 0; j < N; ++j) csr_off[j + 1] += csr_off[j];
+    {
+        std::vector<int32_t> fill(N, 0);
+        for (int t = 0; t < p.Ttot; ++t)
+            for (int cc = 0; cc < 3; ++cc) {
+                const int j = tri[3 * t + cc];
+                csr_ent[csr_off[j] + fill[j]++] = 3 * t + cc;
+            }
+    }
+    HIPCHK(c, hipMemcpyAsync(P.boxes, bd.data(), bd.size() * sizeof(BoxDev), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.drops, dd.data(), dd.size() * sizeof(DropDev), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.qh, qh.data(), qh.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.ql, ql.data(), ql.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.tri, tri.data(), 3 * (size_t)p.Ttot * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.csr_off, csr_off.data(), csr_off.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.csr_ent, csr_ent.data(), 3 * (size_t)p.Ttot * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.blk_drop, blk_drop.data(), (size_t)p.nblk * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.chunks, chunks.data(), (size_t)p.n_chunks * sizeof(TriChunk), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.tchunk_box, tchunk.data(), tchunk.size() * 4, hipMemcpyHostToDevice, c->stream));
+    // fluid at rest: all deviations zero; no tile stamped; band zeroed
+    for (auto &H : p.boxes) {
+        for (int k = 0; k < 2; ++k)
+            HIPCHK(c, hipMemsetAsync(at(H.off_f[k]), 0, (size_t)Q * H.plane * elem_bytes(p.storage), c->stream));
+        HIPCHK(c, hipMemsetAsync(at(H.off_stamp), 0xff, (size_t)H.n_tiles * 4, c->stream));
+        HIPCHK(c, hipMemsetAsync(at(H.off_F), 0, (size_t)H.n_tiles * 3 * TILE_CELLS * R, c->stream));
+        HIPCHK(c, hipMemsetAsync(at(H.off_u), 0, (size_t)H.n_tiles * 3 * TILE_CELLS * R, c->stream));
+    }
+    HIPCHK(c, hipMemsetAsync(P.ctr, 0, 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(P.status, 0, 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(P.phi, 0, (size_t)3 * N * R, c->stream));
+    // reference volumes V0 from the initial mesh (same FP64 sum as the penalty)
+    HIPCHK(c, launch_tri_sums(P, is_f64(c), c->stream));
+    HIPCHK(c, launch_set_v0(P, is_f64(c), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+
+    // default launch shape of the stream-collide kernel
+    int nxmax = 0;
+    for (auto &H : p.boxes) nxmax = std::max(nxmax, H.b.nx);
+    c->L.bx = nxmax <= 32 ? 32 : (nxmax <= 64 ? 64 : (nxmax <= 128 ? 128 : 256));
+    c->L.by = std::max(1, 256 / c->L.bx);
+    c->rows_per_group = c->L.by;
+    st = upload_rows(c);
+    if (st == IBLB_OK && (p.flags & IBLB_FLAG_AUTOTUNE)) st = autotune(c);
+    if (st == IBLB_OK) st = build_graphs(c);
+    if (st == IBLB_OK) {
+        if (hipHostMalloc((void **)&c->host_obs,
+                          ((size_t)P.n_drops * OBS_DROP + (size_t)P.n_boxes * OBS_BOX) * 8 + 64,
+                          hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&c->host_status, 64, hipHostMallocDefault) != hipSuccess)
+            st = set_err(c, IBLB_E_DEVICE, "pinned host buffer allocation failed");
+    }
+    if (st != IBLB_OK) {
+        g_last_error = c->err;
+        iblb_destroy(c);
+        return st;
+    }
+    *out = c;
+    return IBLB_OK;
+}
+
+iblb_status iblb_step(iblb_ctx *c, int64_t n) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (n < 0) return set_err(c, IBLB_E_INVAL, "n_steps < 0");
+    if (c->unstable) return set_err(c, IBLB_E_STATE, "context is unstable; no further steps");
+    for (int64_t k = 0; k < n; ++k) {
+        if (c->exec[c->parity]) {
+            HIPCHK(c, hipGraphLaunch(c->exec[c->parity], c->stream));
+        } else {
+            iblb_status st = enqueue_step(c, c->stream, c->parity);
+            if (st != IBLB_OK) return st;
+        }
+        c->parity ^= 1;
+        ++c->step;
+        if (c->plan.nblk > 0) {
+            c->last_step_epoch = c->epoch;
+            ++c->epoch;
+        }
+    }
+    return IBLB_OK;
+}
+
+iblb_status iblb_observables(iblb_ctx *c, iblb_obs *per_drop, int32_t n_drops, iblb_box_obs *per_box,
+                             int32_t n_boxes) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if ((per_drop && n_drops != c->P.n_drops) || (per_box && n_boxes != c->P.n_boxes))
+        return set_err(c, IBLB_E_INVAL, "output counts do not match the configuration");
+    HIPCHK(c, launch_box_obs(c->P, c->plan.storage, c->parity, (float)(1.0 / c->plan.scale), c->stream));
+    HIPCHK(c, launch_drop_obs(c->P, is_f64(c), c->stream));
+    const size_t nobs = (size_t)c->P.n_drops * OBS_DROP + (size_t)c->P.n_boxes * OBS_BOX;
+    HIPCHK(c, hipMemcpyAsync(c->host_obs, c->P.obs_out, nobs * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->host_status, c->P.status, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const uint32_t bits = *c->host_status;
+    if (per_drop)
+        for (int d = 0; d < c->P.n_drops; ++d) {
+            const double *o = c->host_obs + (size_t)d * OBS_DROP;
+            iblb_obs &r = per_drop[d];
+            r.step = c->step;
+            r.volume = o[0];
+            r.area = o[1];
+            r.z_min = o[2];
+            r.z_max = o[3];
+            r.height = o[3] - o[2];
+            r.centroid[0] = o[4];
+            r.centroid[1] = o[5];
+            r.centroid[2] = o[6];
+            r.n_crossings = (int32_t)o[8];
+            r.contact_radius = o[8] > 0 ? o[7] / o[8] : 0.0;
+            r.theta_app = r.contact_radius > 0 ? 2.0 * std::atan(r.height / r.contact_radius) : 0.0;
+            r.status_bits = bits;
+        }
+    if (per_box)
+        for (int b = 0; b < c->P.n_boxes; ++b) {
+            const double *o = c->host_obs + (size_t)c->P.n_drops * OBS_DROP + (size_t)b * OBS_BOX;
+            per_box[b].step = c->step;
+            per_box[b].mass = o[0];
+            per_box[b].max_u = o[1];
+            per_box[b].status_bits = bits;
+            per_box[b].reserved = 0;
+        }
+    if (bits) {
+        c->unstable = true;
+        return set_err(c, IBLB_E_UNSTABLE, "device status bits 0x" + std::to_string(bits) +
+                                               " (1 rho, 2 Mach, 4 wall, 8 jump)");
+    }
+    return IBLB_OK;
+}
+
+iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_out) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (box < 0 || box >= c->P.n_boxes || (!f_out && !u_out)) return set_err(c, IBLB_E_INVAL, "bad box or outputs");
+    const BoxHost &H = c->plan.boxes[box];
+    const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz;
+    const size_t cells = (size_t)nx * ny * nz;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (f_out) {
+        const size_t eb = elem_bytes(c->plan.storage);
+        std::vector<char> raw((size_t)Q * H.plane * eb);
+        HIPCHK(c, hipMemcpy(raw.data(), c->ws + H.off_f[c->parity], raw.size(), hipMemcpyDeviceToHost));
+        const bool zper = H.b.zbc == IBLB_Z_PERIODIC;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const size_t cell = ((size_t)z * ny + y) * nx + x;
+                    for (int i = 0; i < Q; ++i) {
+                        const int zs = z - cz_of(i);
+                        size_t src;
+                        if (!zper && (zs < 0 || zs >= nz))
+                            src = (size_t)opp_of(i) * H.plane + ((size_t)z * ny + y) * H.sx + x;
+                        else
+                            src = (size_t)i * H.plane +
+                                  ((size_t)wrap(zs, nz) * ny + wrap(y - cy_of(i), ny)) * H.sx +
+                                  wrap(x - cx_of(i), nx);
+                        f_out[(size_t)i * cells + cell] = w_of(i) * H.b.rho0 + decode(c, raw.data(), src);
+                    }
+                }
+    }
+    if (u_out) {
+        const int R = c->plan.real;
+        std::vector<char> ub((size_t)H.n_tiles * 3 * TILE_CELLS * R);
+        std::vector<int32_t> stamp(H.n_tiles);
+        HIPCHK(c, hipMemcpy(ub.data(), c->ws + H.off_u, ub.size(), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(stamp.data(), c->ws + H.off_stamp, stamp.size() * 4, hipMemcpyDeviceToHost));
+        const bool all = (c->plan.flags & IBLB_FLAG_FULL_U) && c->step > 0;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const size_t cell = ((size_t)z * ny + y) * nx + x;
+                    const size_t tile = ((size_t)(z >> 2) * H.tny + (y >> 2)) * H.tnx + (x >> 2);
+                    const int loc = ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
+                    const bool ok = all || (c->last_step_epoch >= 0 && stamp[tile] == c->last_step_epoch);
+                    for (int a = 0; a < 3; ++a) {
+                        const size_t k = (tile * 3 + a) * TILE_CELLS + loc;
+                        const double v = R == 8 ? ((const double *)ub.data())[k] : ((const float *)ub.data())[k];
+                        u_out[(size_t)a * cells + cell] = ok ? v : NAN;
+                    }
+                }
+    }
+    return IBLB_OK;
+}
+
+iblb_status iblb_write_state(iblb_ctx *c, int32_t box, const double *f_in) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (box < 0 || box >= c->P.n_boxes || !f_in) return set_err(c, IBLB_E_INVAL, "bad box or input");
+    const BoxHost &H = c->plan.boxes[box];
+    const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz;
+    const size_t cells = (size_t)nx * ny * nz;
+    for (size_t k = 0; k < (size_t)Q * cells; ++k)
+        if (!std::isfinite(f_in[k])) return set_err(c, IBLB_E_INVAL, "populations not finite");
+    const size_t eb = elem_bytes(c->plan.storage);
+    std::vector<char> raw((size_t)Q * H.plane * eb, 0);
+    const bool zper = H.b.zbc == IBLB_Z_PERIODIC;
+    // inverse of the pull: the stored value at (i, y) is f_i(y + c_i), or,
+    // where y + c_i lies in a wall, f_opp(i)(y)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                for (int i = 0; i < Q; ++i) {
+                    const int zt = z + cz_of(i);
+                    double v;
+                    if (!zper && (zt < 0 || zt >= nz))
+                        v = f_in[(size_t)opp_of(i) * cells + ((size_t)z * ny + y) * nx + x];
+                    else
+                        v = f_in[(size_t)i * cells +
+                                 ((size_t)wrap(zt, nz) * ny + wrap(y + cy_of(i), ny)) * nx +
+                                 wrap(x + cx_of(i), nx)];
+                    encode(c, raw.data(), (size_t)i * H.plane + ((size_t)z * ny + y) * H.sx + x,
+                           v - w_of(i) * H.b.rho0);
+                }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->ws + H.off_f[c->parity], raw.data(), raw.size(), hipMemcpyHostToDevice));
+    return IBLB_OK;
+}
+
+iblb_status iblb_read_nodes(iblb_ctx *c, int32_t d, double *nodes_out) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (d < 0 || d >= c->P.n_drops || !nodes_out) return set_err(c, IBLB_E_INVAL, "bad droplet or output");
+    const DropHost &H = c->plan.drops[d];
+    const int N = c->P.Ntot, R = c->plan.real;
+    std::vector<char> qh((size_t)3 * N * R), ql((size_t)3 * N * R);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(qh.data(), c->P.qh, qh.size(), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(ql.data(), c->P.ql, ql.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < H.d.n_nodes; ++k)
+        for (int a = 0; a < 3; ++a) {
+            const size_t idx = (size_t)a * N + H.node_off + k;
+            nodes_out[3 * (size_t)H.perm[k] + a] =
+                R == 8 ? ((double *)qh.data())[idx] + ((double *)ql.data())[idx]
+                       : (double)((float *)qh.data())[idx] + (double)((float *)ql.data())[idx];
+        }
+    return IBLB_OK;
+}
+
+iblb_status iblb_write_nodes(iblb_ctx *c, int32_t d, const double *nodes_in) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (d < 0 || d >= c->P.n_drops || !nodes_in) return set_err(c, IBLB_E_INVAL, "bad droplet or input");
+    const DropHost &H = c->plan.drops[d];
+    const iblb_box &B = c->plan.boxes[H.d.box].b;
+    for (int k = 0; k < 3 * H.d.n_nodes; ++k)
+        if (!std::isfinite(nodes_in[k])) return set_err(c, IBLB_E_INVAL, "node coordinate not finite");
+    if (B.zbc == IBLB_Z_WALLS)
+        for (int k = 0; k < H.d.n_nodes; ++k)
+            if (!(nodes_in[3 * k + 2] > 0.0 && nodes_in[3 * k + 2] < B.nz))
+                return set_err(c, IBLB_E_MESH, "node not strictly between the walls");
+    const int N = c->P.Ntot, R = c->plan.real;
+    std::vector<char> qh((size_t)3 * N * R), ql((size_t)3 * N * R);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(qh.data(), c->P.qh, qh.size(), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(ql.data(), c->P.ql, ql.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < H.d.n_nodes; ++k)
+        for (int a = 0; a < 3; ++a) {
+            const size_t idx = (size_t)a * N + H.node_off + k;
+            const double v = nodes_in[3 * (size_t)H.perm[k] + a];
+            if (R == 8) {
+                ((double *)qh.data())[idx] = v;
+                ((double *)ql.data())[idx] = 0.0;
+            } else {
+                const float h = (float)v;
+                ((float *)qh.data())[idx] = h;
+                ((float *)ql.data())[idx] = (float)(v - (double)h);
+            }
+        }
+    HIPCHK(c, hipMemcpy(c->P.qh, qh.data(), qh.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->P.ql, ql.data(), ql.size(), hipMemcpyHostToDevice));
+    return IBLB_OK;
+}
+
+iblb_status iblb_compute_forces(iblb_ctx *c, int32_t d, double *phi_out) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (d < 0 || d >= c->P.n_drops || !phi_out) return set_err(c, IBLB_E_INVAL, "bad droplet or output");
+    const bool f64 = is_f64(c);
+    if (c->plan.any_kvol) HIPCHK(c, launch_tri_sums(c->P, f64, c->stream));
+    HIPCHK(c, launch_node(c->P, f64, 1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const DropHost &H = c->plan.drops[d];
+    const int N = c->P.Ntot, R = c->plan.real;
+    std::vector<char> phi((size_t)3 * N * R);
+    HIPCHK(c, hipMemcpy(phi.data(), c->P.phi, phi.size(), hipMemcpyDeviceToHost));
+    for (int k = 0; k < H.d.n_nodes; ++k)
+        for (int a = 0; a < 3; ++a) {
+            const size_t idx = (size_t)a * N + H.node_off + k;
+            phi_out[3 * (size_t)H.perm[k] + a] =
+                R == 8 ? ((double *)phi.data())[idx] : (double)((float *)phi.data())[idx];
+        }
+    return IBLB_OK;
+}
+
+iblb_status iblb_compute_spread(iblb_ctx *c, int32_t b, double *F_out, uint8_t *flags_out) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (b < 0 || b >= c->P.n_boxes || (!F_out && !flags_out)) return set_err(c, IBLB_E_INVAL, "bad box or outputs");
+    const bool f64 = is_f64(c);
+    if (c->plan.any_kvol) HIPCHK(c, launch_tri_sums(c->P, f64, c->stream));
+    HIPCHK(c, launch_node(c->P, f64, 0, c->stream));
+    HIPCHK(c, launch_spread(c->P, f64, c->stream));
+    HIPCHK(c, launch_epoch(c->P, c->stream));
+    const int32_t used = c->epoch;
+    ++c->epoch;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const BoxHost &H = c->plan.boxes[b];
+    const int R = c->plan.real;
+    std::vector<char> Fb((size_t)H.n_tiles * 3 * TILE_CELLS * R);
+    std::vector<int32_t> stamp(H.n_tiles);
+    HIPCHK(c, hipMemcpy(Fb.data(), c->ws + H.off_F, Fb.size(), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(stamp.data(), c->ws + H.off_stamp, stamp.size() * 4, hipMemcpyDeviceToHost));
+    const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz;
+    const size_t cells = (size_t)nx * ny * nz;
+    if (flags_out)
+        for (int t = 0; t < H.n_tiles; ++t) flags_out[t] = stamp[t] == used ? 1 : 0;
+    if (F_out)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const size_t cell = ((size_t)z * ny + y) * nx + x;
+                    const size_t tile = ((size_t)(z >> 2) * H.tny + (y >> 2)) * H.tnx + (x >> 2);
+                    const int loc = ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
+                    for (int a = 0; a < 3; ++a) {
+                        const size_t k = (tile * 3 + a) * TILE_CELLS + loc;
+                        const double v = R == 8 ? ((double *)Fb.data())[k] : ((float *)Fb.data())[k];
+                        F_out[(size_t)a * cells + cell] = stamp[tile] == used ? v : 0.0;
+                    }
+                }
+    return IBLB_OK;
+}
+
+iblb_status iblb_interpolate(iblb_ctx *c, int32_t d, const double *u_in, double *U_out) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (d < 0 || d >= c->P.n_drops || !u_in || !U_out) return set_err(c, IBLB_E_INVAL, "bad droplet or arrays");
+    const DropHost &Dh = c->plan.drops[d];
+    const BoxHost &H = c->plan.boxes[Dh.d.box];
+    const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz, R = c->plan.real;
+    const size_t cells = (size_t)nx * ny * nz;
+    std::vector<char> ub((size_t)H.n_tiles * 3 * TILE_CELLS * R, 0);
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const size_t cell = ((size_t)z * ny + y) * nx + x;
+                const size_t tile = ((size_t)(z >> 2) * H.tny + (y >> 2)) * H.tnx + (x >> 2);
+                const int loc = ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
+                for (int a = 0; a < 3; ++a) {
+                    const size_t k = (tile * 3 + a) * TILE_CELLS + loc;
+                    if (R == 8) ((double *)ub.data())[k] = u_in[(size_t)a * cells + cell];
+                    else ((float *)ub.data())[k] = (float)u_in[(size_t)a * cells + cell];
+                }
+            }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->ws + H.off_u, ub.data(), ub.size(), hipMemcpyHostToDevice));
+    const bool f64 = is_f64(c);
+    double *Udev = (double *)(c->ws + c->plan.off_uout);
+    HIPCHK(c, launch_node(c->P, f64, 1, c->stream));
+    HIPCHK(c, launch_interp(c->P, f64, 1, Udev, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> U((size_t)3 * c->P.Ntot);
+    HIPCHK(c, hipMemcpy(U.data(), Udev, U.size() * 8, hipMemcpyDeviceToHost));
+    for (int k = 0; k < Dh.d.n_nodes; ++k)
+        for (int a = 0; a < 3; ++a) U_out[3 * (size_t)Dh.perm[k] + a] = U[3 * (size_t)(Dh.node_off + k) + a];
+    return IBLB_OK;
+}
+
+iblb_status iblb_read_bins(iblb_ctx *c, int32_t d, int32_t *base_out) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (d < 0 || d >= c->P.n_drops || !base_out) return set_err(c, IBLB_E_INVAL, "bad droplet or output");
+    HIPCHK(c, launch_node(c->P, is_f64(c), 1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const DropHost &H = c->plan.drops[d];
+    const iblb_box &B = c->plan.boxes[H.d.box].b;
+    const int N = c->P.Ntot;
+    std::vector<int32_t> base((size_t)3 * N);
+    HIPCHK(c, hipMemcpy(base.data(), c->P.base, base.size() * 4, hipMemcpyDeviceToHost));
+    for (int k = 0; k < H.d.n_nodes; ++k) {
+        const size_t u = 3 * (size_t)H.perm[k];
+        base_out[u] = wrap(base[H.node_off + k], B.nx);
+        base_out[u + 1] = wrap(base[(size_t)N + H.node_off + k], B.ny);
+        base_out[u + 2] = base[2 * (size_t)N + H.node_off + k];
+    }
+    return IBLB_OK;
+}
+
+iblb_status iblb_read_csr(iblb_ctx *c, int32_t d, int32_t *offsets, int32_t *entries) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (d < 0 || d >= c->P.n_drops || !offsets || !entries) return set_err(c, IBLB_E_INVAL, "bad droplet or outputs");
+    const DropHost &H = c->plan.drops[d];
+    const int N = c->P.Ntot;
+    std::vector<int32_t> off((size_t)N + 1), ent((size_t)3 * c->P.Ttot);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(off.data(), c->P.csr_off, off.size() * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(ent.data(), c->P.csr_ent, ent.size() * 4, hipMemcpyDeviceToHost));
+    offsets[0] = 0;
+    for (int u = 0; u < H.d.n_nodes; ++u) {
+        const int k = H.node_off + H.inv[u];
+        offsets[u + 1] = offsets[u] + (off[k + 1] - off[k]);
+        for (int e = off[k]; e < off[k + 1]; ++e) {
+            const int code = ent[e], t = code / 3;
+            entries[offsets[u] + (e - off[k])] = 3 * (t - H.tri_off) + (code - 3 * t);
+        }
+    }
+    return IBLB_OK;
+}
+
+iblb_status iblb_set_launch(iblb_ctx *c, int32_t bx, int32_t by) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    iblb_status st = check_launch(c, bx, by);
+    if (st != IBLB_OK) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->L.bx = bx;
+    c->L.by = by;
+    c->rows_per_group = by;
+    st = upload_rows(c);
+    if (st == IBLB_OK) st = build_graphs(c);
+    return st;
+}
+
+iblb_status iblb_get_launch(const iblb_ctx *c, int32_t *bx, int32_t *by) {
+    if (!c || !bx || !by) return set_err(nullptr, IBLB_E_INVAL, "NULL argument");
+    *bx = c->L.bx;
+    *by = c->L.by;
+    return IBLB_OK;
+}
+
+iblb_status iblb_time_stream_collide(iblb_ctx *c, int32_t reps, double *ms) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (reps < 1 || !ms) return set_err(c, IBLB_E_INVAL, "reps >= 1 and an output are required");
+    return time_k1(c, reps, ms);
+}
+
+iblb_status iblb_destroy(iblb_ctx *c) {
+    if (!c) return IBLB_OK;
+    drop_graphs(c);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
+    if (c->host_obs) (void)hipHostFree(c->host_obs);
+    if (c->host_status) (void)hipHostFree(c->host_status);
+    delete c;
+    return IBLB_OK;
+}
+
+const char *iblb_last_error(const iblb_ctx *c) { return c ? c->err.c_str() : g_last_error.c_str(); }
+
+}  // extern "C"

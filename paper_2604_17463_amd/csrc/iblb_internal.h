@@ -1,0 +1,131 @@
+// Internal layout shared by the host library and the gfx950 kernels.
+//
+// Everything lives in one caller-owned device workspace.  Per box:
+//   - two population buffers A/B, structure of arrays [19][nz][ny][sx]
+//     (sx = x pitch rounded up to a 128-byte row), storing deviations
+//     f_i - w_i rho0 (scaled for FP16); a buffer holds the post-collision
+//     populations of the last step and the next step pulls from it;
+//   - 4x4x4 tiles (64 cells = one wavefront): an epoch stamp per tile and,
+//     in tile-major order [tile][3][64], the spread force F and the velocity
+//     u written by the stream-collide kernel in stamped tiles.
+// Per droplet, nodes are renumbered once (Morton order of the initial
+// positions) and grouped in blocks of 64 (one wavefront), padded per
+// droplet.  Node arrays are SoA over the padded global node index.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace iblb {
+
+constexpr int Q = 19;
+constexpr int TILE = 4;
+constexpr int TILE_CELLS = 64;
+constexpr int NB = 64;           // nodes per block
+constexpr int TRI_CHUNK = 256;   // triangles per FP64 partial-sum chunk
+
+// Velocity set in the library's order: 0 = rest, i and i+9 opposite (i=1..9).
+__host__ __device__ constexpr int cx_of(int i) {
+    constexpr int t[Q] = {0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
+    return t[i];
+}
+__host__ __device__ constexpr int cy_of(int i) {
+    constexpr int t[Q] = {0, 0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+    return t[i];
+}
+__host__ __device__ constexpr int cz_of(int i) {
+    constexpr int t[Q] = {0, 0, 0, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 0, 0, -1, 1, -1, 1};
+    return t[i];
+}
+__host__ __device__ constexpr int opp_of(int i) { return i == 0 ? 0 : (i <= 9 ? i + 9 : i - 9); }
+// 1/3 at rest, 1/18 along the axes, 1/36 along face diagonals.
+__host__ __device__ constexpr double w_of(int i) {
+    return i == 0 ? 1.0 / 3.0
+                  : ((cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_of(i) * cz_of(i)) == 1
+                         ? 1.0 / 18.0
+                         : 1.0 / 36.0);
+}
+
+enum : uint32_t { BIT_RHO = 1u, BIT_MACH = 2u, BIT_WALL = 4u, BIT_JUMP = 8u };
+
+struct BoxDev {
+    int32_t nx, ny, nz, zbc;
+    int32_t sx;                 // x pitch (elements)
+    int32_t tnx, tny, tnz;      // tiles per axis
+    int64_t plane;              // elements per direction plane
+    int32_t n_tiles, tile_base; // tile_base: first global tile (multiple of 64)
+    int32_t blk_begin, blk_end; // node blocks of the box's droplets
+    void *f[2];                 // population buffers
+    void *Fband, *uband;        // [n_tiles][3][64] of Real
+    int32_t *stamp;             // [n_tiles]
+    double tau, rho0, g[3];
+    double omega, guo;          // 1/tau, 1 - 1/(2 tau)
+    double cells_rho0;          // nx*ny*nz*rho0
+};
+
+struct DropDev {
+    int32_t box, n_nodes, n_tris, n_exp;
+    int32_t m_exp, node_off, blk_off, n_blocks;
+    int32_t tri_off, chunk_off, n_chunks, pad;
+    double sigma, A, xi, kvol, V0;
+    double ref[3];              // origin for the FP64 volume sum
+};
+
+struct RowGroup {
+    int32_t box, r0, r1, pad;   // rows r = z*ny + y in [r0, r1)
+};
+
+struct TriChunk {
+    int32_t drop, t0, t1, pad;  // global triangle range
+};
+
+struct DevPtrs {
+    BoxDev *boxes;
+    DropDev *drops;
+    int32_t n_boxes, n_drops;
+    // node arrays, SoA [3][Ntot] unless stated
+    void *qh, *ql;              // position, high and low parts (Real)
+    void *phi;                  // nodal force (Real)
+    void *wgt;                  // [12][Ntot] Peskin weights x0..3,y0..3,z0..3 (Real)
+    int32_t *base;              // floor(q - 1/2), unwrapped
+    int32_t *s0;                // first stencil cell base-1, wrapped where periodic
+    int32_t *bbox;              // [6][nblk]: x0,x1,y0,y1,z0,z1 of stencil cells
+    int32_t *blk_drop;          // [nblk]
+    int32_t *tri;               // [Ttot][3] global node ids
+    int32_t *csr_off;           // [Ntot+1]
+    int32_t *csr_ent;           // [3 Ttot]: 3*t + corner
+    TriChunk *chunks;
+    double *tri_part;           // [2][n_chunks]: volume, area
+    RowGroup *rows;
+    int32_t *tchunk_box;        // [total_tiles/64] box of each 64-tile chunk
+    int32_t *ctr;               // step epoch
+    uint32_t *status;
+    double *obs_part;           // observables scratch
+    double *obs_out;            // per droplet [12], per box [2]
+    int32_t Ntot, nblk, Ttot, n_chunks;
+    int32_t n_rowgroups, total_tiles, obs_groups, pad;
+};
+
+// Launch entry points implemented in iblb_kernels.hip.
+struct Launch {
+    int bx, by;                 // stream-collide block shape
+    int grid;                   // stream-collide grid (<= n_rowgroups)
+};
+
+hipError_t launch_tri_sums(const DevPtrs &P, bool f64, hipStream_t s);
+hipError_t launch_set_v0(const DevPtrs &P, bool f64, hipStream_t s);
+hipError_t launch_node(const DevPtrs &P, bool f64, int mode, hipStream_t s);
+hipError_t launch_spread(const DevPtrs &P, bool f64, hipStream_t s);
+hipError_t launch_stream_collide(const DevPtrs &P, int storage, int parity, int full_u,
+                                 float scale, const Launch &L, hipStream_t s);
+hipError_t launch_interp(const DevPtrs &P, bool f64, int mode, double *Uout, hipStream_t s);
+hipError_t launch_epoch(const DevPtrs &P, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_box_obs(const DevPtrs &P, int storage, int parity, float inv_scale,
+                          hipStream_t s);
+hipError_t launch_drop_obs(const DevPtrs &P, bool f64, hipStream_t s);
+
+constexpr int OBS_DROP = 12; // vol, area, zmin, zmax, cx, cy, cz, rsum, count, -, -, -
+constexpr int OBS_BOX = 2;   // mass, max_u
+constexpr int OBS_GROUPS = 512;
+
+}  // namespace iblb

@@ -1,0 +1,315 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle on the
+same seeded inputs, through the C ABI.  Tolerances: FP64 path 1e-10
+relative L2 or tighter, FP32 path 1e-5 relative for fields, integer outputs
+bit-exact."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from iblb_inputs import configs, mesh
+from iblb_inputs.configs import Box, Droplet, Workload
+
+from _helpers import deviation, lib_to_oracle_perm, rel_l2, say, to_lib, to_oracle
+
+pytestmark = pytest.mark.gpu
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+FULL_U, GRAPH, AUTOTUNE = 4, 1, 2
+
+
+def sim(wl, storage, flags=0, dev_scale=None):
+    import paper_2604_17463_amd as P
+    if dev_scale is None:
+        dev_scale = 4096.0 if storage == F16 else 1.0
+    return P.Simulation(wl, storage=storage, flags=flags, dev_scale=dev_scale)
+
+
+@pytest.fixture(scope="module")
+def perm():
+    return lib_to_oracle_perm()
+
+
+def _empty_box(nx=12, ny=10, nz=8, zbc=0, tau=0.8, g=(1e-5, -2e-5, 3e-5)):
+    return Workload("box", [Box(nx, ny, nz, tau=tau, zbc=zbc, body_force=g)], [], storage=F64)
+
+
+def _perturbed(box, seed, perm):
+    _, w, _ = oracle.lattice()
+    eta = configs.perturbed_populations(box, seed)
+    return (w * box.rho0)[:, None, None, None] * (1.0 + eta)
+
+
+@pytest.mark.parametrize("storage", [F64, F32, F16, BF16])
+def test_rest_state_is_exact(storage):
+    say("rest state", storage)
+    s = sim(_empty_box(g=(0, 0, 0)), storage, flags=FULL_U)
+    s.step(7)
+    f, u = s.read_state(0, want_u=True)
+    _, w, _ = oracle.lattice()
+    c, wl = __import__("paper_2604_17463_amd").velocity_set()
+    assert np.array_equal(f, np.broadcast_to(wl[:, None, None, None], f.shape))
+    assert np.all(u == 0)
+    _, boxes = s.observables()
+    assert boxes[0]["mass"] == 12 * 10 * 8 and boxes[0]["max_u"] == 0
+
+
+@pytest.mark.parametrize("zbc", [0, 1])
+@pytest.mark.parametrize("storage", [F64, F32])
+def test_lattice_steps_match_oracle(storage, zbc, perm):
+    say("lattice steps", storage, zbc)
+    wl = _empty_box(zbc=zbc)
+    box = wl.boxes[0]
+    s = sim(wl, storage, flags=FULL_U)
+    s.write_state(to_lib(_perturbed(box, 11, perm), perm))
+    f0 = to_oracle(s.read_state(0), perm)  # what the GPU actually holds
+    f = f0
+    for n in range(1, 6):
+        f, _, u = oracle.lb_step(f, box.tau, zbc, None, box.body_force)
+        s.step(1)
+        fg, ug = s.read_state(0, want_u=True)
+        fg = to_oracle(fg, perm)
+        tol = 1e-13 if storage == F64 else 2e-6
+        assert rel_l2(deviation(fg), deviation(f)) < tol * n, n
+        assert rel_l2(ug, u) < (1e-12 if storage == F64 else 2e-6), n
+
+
+@pytest.mark.parametrize("storage,tol", [(F64, 1e-10), (F32, 1e-5)])
+def test_poiseuille_closed_form_gpu(storage, tol):
+    say("poiseuille", storage)
+    H, tau, g = 24, 0.8, 1e-6
+    wl = _empty_box(4, 4, H, 0, tau, (g, 0.0, 0.0))
+    s = sim(wl, storage, flags=FULL_U | GRAPH)
+    nu = (tau - 0.5) / 3
+    s.step(int(36 * H * H / (math.pi ** 2 * nu)))
+    _, u = s.read_state(0, want_u=True)
+    z = np.arange(H) + 0.5
+    lam = (tau - 0.5) ** 2
+    exact = g * z * (H - z) / (2 * nu) + (g / nu) * (2 * lam / 3 - 1 / 8)
+    ux = u[0, :, 0, 0]
+    assert rel_l2(ux, exact) < tol
+    assert np.abs(u[0] - u[0, :, :1, :1]).max() <= tol * np.abs(exact).max()
+
+
+def _c1_jittered(seed=3, amp=0.2):
+    wl = configs.plain_c1()
+    d = wl.droplets[0]
+    d.nodes = configs.jitter_nodes(d.nodes, seed, amp)
+    return wl
+
+
+@pytest.mark.parametrize("storage", [F64, F32])
+@pytest.mark.parametrize("kvol", [0.0, 0.004])
+def test_nodal_forces_match_oracle(storage, kvol):
+    say("forces", storage, kvol)
+    wl = _c1_jittered()
+    wl.droplets[0].k_vol = kvol
+    s = sim(wl, storage)
+    d = wl.droplets[0]
+    q0 = d.nodes.copy()
+    # move the nodes after init so V differs from V0
+    q = configs.jitter_nodes(q0, 8, 0.1)
+    s.write_nodes(q)
+    qg = s.read_nodes(0)
+    A = oracle.wetting_A(d.sigma, d.theta_eq, d.xi, d.n_exp, d.m_exp)
+    want = oracle.node_forces(d.tris, qg, d.sigma, A, d.xi, d.n_exp, d.m_exp, kvol,
+                              oracle.volume(d.tris, q0))["phi"]
+    got = s.compute_forces(0)
+    scale = np.abs(want).max()
+    assert np.abs(got - want).max() < (1e-12 if storage == F64 else 2e-5) * scale
+
+
+@pytest.mark.parametrize("storage", [F64, F32])
+def test_bins_and_csr_are_bit_exact(storage):
+    say("bins/csr", storage)
+    wl = _c1_jittered()
+    s = sim(wl, storage)
+    q = wl.droplets[0].nodes.copy()
+    # put some coordinates exactly on cell faces and centres (ties)
+    q[:40, 0] = np.round(q[:40, 0])
+    q[40:80, 1] = np.floor(q[40:80, 1]) + 0.5
+    q[80:120, 2] = np.floor(q[80:120, 2]) + 0.5
+    q[120:130, 0] += 32.0  # unwrapped beyond the box
+    s.write_nodes(q)
+    qg = s.read_nodes(0)
+    assert np.array_equal(oracle.base_cells(qg, 32, 32), s.read_bins(0))
+    off, ent = oracle.csr(len(q), wl.droplets[0].tris)
+    goff, gent = s.read_csr(0)
+    assert np.array_equal(off, goff) and np.array_equal(ent, gent)
+
+
+@pytest.mark.parametrize("storage", [F64, F32])
+@pytest.mark.parametrize("which", ["c1", "cap"])
+def test_spread_matches_oracle(storage, which):
+    say("spread", storage, which)
+    if which == "c1":
+        wl = _c1_jittered()
+    else:
+        v, t = mesh.cap_on_wall(3, 8.0, math.radians(150), 14.5, 17.25, 0.4)
+        wl = Workload("cap", [Box(32, 28, 24, tau=0.9)],
+                      [Droplet(0, v, t, sigma=0.01, theta_eq=1.0, xi=0.4)], storage=F64)
+    s = sim(wl, storage)
+    box = wl.boxes[0]
+    qg = s.read_nodes(0)
+    phi = s.compute_forces(0)
+    F, flags = s.compute_spread(0)
+    Fo, tw = oracle.spread((box.nz, box.ny, box.nx), box.zbc, qg, phi)
+    assert rel_l2(F, Fo) < (1e-13 if storage == F64 else 1e-6)
+    assert np.array_equal(flags, oracle.touched_tiles(qg, (box.nz, box.ny, box.nx), box.zbc))
+    assert np.allclose(F.sum(axis=(1, 2, 3)) + tw, phi.sum(0), rtol=0,
+                       atol=(1e-14 if storage == F64 else 1e-7) * np.abs(phi).sum())
+
+
+@pytest.mark.parametrize("storage", [F64, F32])
+@pytest.mark.parametrize("zbc", [0, 1])
+def test_interpolation_matches_oracle(storage, zbc):
+    say("interp", storage, zbc)
+    wl = _c1_jittered()
+    wl.boxes[0].zbc = zbc
+    s = sim(wl, storage)
+    box = wl.boxes[0]
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((3, box.nz, box.ny, box.nx)) * 1e-3
+    qg = s.read_nodes(0)
+    U = s.interpolate(u, 0)
+    Uo = oracle.interp(u, zbc, qg)
+    assert rel_l2(U, Uo) < (1e-13 if storage == F64 else 1e-6)
+
+
+@pytest.mark.parametrize("storage", [F64, F32])
+def test_observables_match_oracle_on_same_positions(storage):
+    say("observables", storage)
+    wl = configs.spreading_c2(steps=1)
+    s = sim(wl, storage)
+    s.step(3)
+    qg = s.read_nodes(0)
+    d = wl.droplets[0]
+    drops, boxes = s.observables()
+    o = oracle.mesh_observables(d.tris, qg, d.xi)
+    for k in ("volume", "area", "z_min", "z_max", "height", "contact_radius", "cx", "cy", "cz"):
+        assert abs(drops[0][k] - o[k]) <= 1e-11 * max(1.0, abs(o[k])), k
+    assert drops[0]["n_crossings"] == o["n_crossings"]
+    f = s.read_state(0)
+    assert abs(boxes[0]["mass"] - oracle.mass(f)) <= 1e-12 * oracle.mass(f)
+    assert abs(boxes[0]["max_u"] - oracle.max_u(f)) <= 1e-9 * max(oracle.max_u(f), 1e-12)
+
+
+def _run_pair(wl, storage, steps, flags=FULL_U):
+    s = sim(wl, storage, flags=flags)
+    ref = oracle.OracleSim(wl)
+    ref.step(steps)
+    s.step(steps)
+    return s, ref
+
+
+def test_plain_c1_fp64_full_parity(perm):
+    say("c1 fp64 200 steps")
+    wl = configs.plain_c1()
+    s, ref = _run_pair(wl, F64, 200)
+    f, u = s.read_state(0, want_u=True)
+    f = to_oracle(f, perm)
+    assert rel_l2(deviation(f), deviation(ref.f[0])) < 1e-10
+    assert rel_l2(u, ref.last_u[0]) < 1e-10
+    q = s.read_nodes(0)
+    assert np.abs(q - ref.q[0]).max() < 1e-10
+    drops, boxes = s.observables()
+    od, ob = ref.observables()
+    assert abs(boxes[0]["mass"] - ob[0]["mass"]) < 1e-13 * ob[0]["mass"]
+    for k in ("volume", "area", "height", "contact_radius", "z_min"):
+        assert abs(drops[0][k] - od[0][k]) < 1e-10 * abs(od[0][k]), k
+
+
+def test_plain_c1_fp32_parity(perm):
+    say("c1 fp32 200 steps")
+    wl = configs.plain_c1()
+    s, ref = _run_pair(wl, F32, 200)
+    f, u = s.read_state(0, want_u=True)
+    f = to_oracle(f, perm)
+    assert rel_l2(f, ref.f[0]) < 1e-6
+    assert rel_l2(deviation(f), deviation(ref.f[0])) < 1e-4
+    assert rel_l2(u, ref.last_u[0]) < 1e-5
+    assert np.abs(s.read_nodes(0) - ref.q[0]).max() < 1e-5
+    drops, boxes = s.observables()
+    od, ob = ref.observables()
+    assert abs(boxes[0]["mass"] - ob[0]["mass"]) < 1e-9 * ob[0]["mass"]
+    assert abs(drops[0]["volume"] - od[0]["volume"]) < 1e-6 * od[0]["volume"]
+    assert abs(drops[0]["height"] - od[0]["height"]) < 1e-5 * od[0]["height"]
+
+
+@pytest.mark.parametrize("storage", [F32, F16])
+def test_graph_replay_is_bitwise_equal_to_eager(storage):
+    say("graph vs eager", storage)
+    wl = configs.plain_c1()
+    a = sim(wl, storage, flags=0)
+    b = sim(wl, storage, flags=GRAPH)
+    a.step(37)
+    b.step(37)
+    assert np.array_equal(a.read_state(0), b.read_state(0))
+    assert np.array_equal(a.read_nodes(0), b.read_nodes(0))
+
+
+def test_runs_are_deterministic():
+    say("determinism")
+    wl = configs.plain_c1()
+    a = sim(wl, F32, flags=GRAPH)
+    b = sim(wl, F32, flags=GRAPH | AUTOTUNE)
+    a.step(50)
+    b.step(50)
+    assert np.array_equal(a.read_state(0), b.read_state(0))
+    assert np.array_equal(a.read_nodes(0), b.read_nodes(0))
+
+
+def _small_batch(seed=4):
+    rng = np.random.default_rng(seed)
+    boxes, drops = [], []
+    for k, (nx, ny, nz) in enumerate([(32, 24, 20), (20, 28, 24), (36, 36, 16)]):
+        r = float(rng.uniform(4, 6))
+        v, t = mesh.sphere_above_wall(2 + k % 2, r, nx / 2 + 0.3, ny / 2 - 0.2, 0.05 * r)
+        boxes.append(Box(nx, ny, nz, tau=float(rng.uniform(0.6, 1.4))))
+        drops.append(Droplet(k, v, t, sigma=0.01, theta_eq=float(rng.uniform(0.6, 2.5)),
+                             xi=0.05 * r, k_vol=0.002 * k))
+    return Workload("small-batch", boxes, drops, storage=F32)
+
+
+@pytest.mark.parametrize("storage", [F64, F32])
+def test_batched_boxes_equal_separate_runs(storage):
+    say("batched vs separate", storage)
+    wl = _small_batch()
+    s = sim(wl, storage, flags=GRAPH)
+    s.step(25)
+    for k in range(len(wl.boxes)):
+        one = Workload("one", [wl.boxes[k]], [Droplet(0, **{f: getattr(wl.droplets[k], f) for f in (
+            "nodes", "tris", "sigma", "theta_eq", "xi", "n_exp", "m_exp", "k_vol")})],
+            storage=storage)
+        t = sim(one, storage)
+        t.step(25)
+        assert np.array_equal(s.read_state(k), t.read_state(0)), k
+        assert np.array_equal(s.read_nodes(k), t.read_nodes(0)), k
+
+
+def test_batched_matches_oracle_fp64(perm):
+    say("batched fp64 vs oracle")
+    wl = _small_batch()
+    s = sim(wl, F64, flags=FULL_U | GRAPH)
+    ref = oracle.OracleSim(wl)
+    s.step(30)
+    ref.step(30)
+    for k in range(len(wl.boxes)):
+        f = to_oracle(s.read_state(k), perm)
+        assert rel_l2(deviation(f), deviation(ref.f[k])) < 1e-10
+        assert np.abs(s.read_nodes(k) - ref.q[k]).max() < 1e-10
+
+
+def test_instability_is_reported_and_sticky():
+    import paper_2604_17463_amd as P
+    say("instability")
+    wl = _empty_box(g=(0.08, 0.0, 0.0), zbc=1)
+    s = sim(wl, F32)
+    s.step(40)
+    with pytest.raises(P.IblbError) as e:
+        s.observables()
+    assert e.value.code == -5
+    with pytest.raises(P.IblbError) as e:
+        s.step(1)
+    assert e.value.code == -6
