@@ -190,8 +190,9 @@ iblb_status iblb_read_bins(struct iblb_ctx *ctx, int32_t d, int32_t *base_out);
 iblb_status iblb_read_csr(struct iblb_ctx *ctx, int32_t d, int32_t *offsets, int32_t *entries);
 
 /* Launch shape of the fused stream-collide kernel: threads along x per row
- * (64..1024, multiple of 64, times rows_per_group <= 1024) and rows handled
- * by one workgroup.  Rebuilds the step graphs.  Synchronising. */
+ * (a multiple of 32) and rows handled by one workgroup; their product must be
+ * a multiple of 64 and at most 256.  Other shapes return IBLB_E_INVAL.
+ * Rebuilds the step graphs.  Synchronising. */
 iblb_status iblb_set_launch(struct iblb_ctx *ctx, int32_t threads_x, int32_t rows_per_group);
 iblb_status iblb_get_launch(const struct iblb_ctx *ctx, int32_t *threads_x,
                             int32_t *rows_per_group);

@@ -55,6 +55,7 @@ struct Plan {
     bool any_kvol = false;
     // workspace offsets
     size_t off_boxes = 0, off_drops = 0, off_qh = 0, off_ql = 0, off_phi = 0, off_wgt = 0,
+           off_trec = 0, off_tile_list = 0, off_tile_count = 0,
            off_base = 0, off_s0 = 0, off_bbox = 0, off_blk_drop = 0, off_tri = 0,
            off_csr_off = 0, off_csr_ent = 0, off_chunks = 0, off_tri_part = 0, off_rows = 0,
            off_tchunk = 0, off_ctr = 0, off_status = 0, off_obs_part = 0, off_obs_out = 0,
@@ -286,6 +287,9 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
     p.off_ql = take(3 * N * p.real);
     p.off_phi = take(3 * N * p.real);
     p.off_wgt = take(12 * N * p.real);
+    p.off_trec = take((size_t)TREC * p.Ttot * p.real);
+    p.off_tile_list = take((size_t)p.total_tiles * 4);
+    p.off_tile_count = take(2 * 4);
     p.off_base = take(3 * N * 4);
     p.off_s0 = take(3 * N * 4);
     p.off_bbox = take(6 * (size_t)p.nblk * 4);
@@ -361,7 +365,7 @@ iblb_status upload_rows(iblb_ctx *c) {
 
 iblb_status enqueue_step(iblb_ctx *c, hipStream_t s, int parity) {
     const bool f64 = is_f64(c);
-    if (c->plan.any_kvol) HIPCHK(c, launch_tri_sums(c->P, f64, s));
+    HIPCHK(c, launch_tri(c->P, f64, s));
     HIPCHK(c, launch_node(c->P, f64, 0, s));
     HIPCHK(c, launch_spread(c->P, f64, s));
     HIPCHK(c, launch_stream_collide(c->P, c->plan.storage, parity,
@@ -401,9 +405,10 @@ iblb_status build_graphs(iblb_ctx *c) {
 }
 
 iblb_status check_launch(iblb_ctx *c, int bx, int by) {
-    if (bx < 32 || bx > 1024 || (bx & 31) || by < 1 || bx * by > 1024 || (bx * by) % 64)
-        return set_err(c, IBLB_E_INVAL, "launch shape: threads_x in [32,1024] multiple of 32, "
-                                        "threads_x*rows a multiple of 64 and <= 1024");
+    if (bx < 32 || (bx & 31) || by < 1 || bx * by > K1_MAX_THREADS || (bx * by) % 64)
+        return set_err(c, IBLB_E_INVAL, "launch shape: threads_x a multiple of 32, "
+                                        "threads_x*rows a multiple of 64 and <= " +
+                                            std::to_string(K1_MAX_THREADS));
     return IBLB_OK;
 }
 
@@ -433,9 +438,9 @@ iblb_status autotune(iblb_ctx *c) {
     const int saved_parity = c->parity;
     double best = 1e300;
     int bbx = c->L.bx, bby = c->L.by;
-    for (int bx : {32, 64, 128, 256, 512}) {
+    for (int bx : {32, 64, 128, 256}) {
         if (bx > (int)round_up((size_t)nxmax, 32)) continue;
-        for (int threads : {256, 512}) {
+        for (int threads : {64, 128, K1_MAX_THREADS}) {
             const int by = threads / bx;
             if (by < 1 || check_launch(c, bx, by) != IBLB_OK) continue;
             c->L.bx = bx;
@@ -558,6 +563,9 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     P.ql = at(p.off_ql);
     P.phi = at(p.off_phi);
     P.wgt = at(p.off_wgt);
+    P.trec = at(p.off_trec);
+    P.tile_list = (int32_t *)at(p.off_tile_list);
+    P.tile_count = (int32_t *)at(p.off_tile_count);
     P.base = (int32_t *)at(p.off_base);
     P.s0 = (int32_t *)at(p.off_s0);
     P.bbox = (int32_t *)at(p.off_bbox);
@@ -693,10 +701,11 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
         HIPCHK(c, hipMemsetAsync(at(H.off_u), 0, (size_t)H.n_tiles * 3 * TILE_CELLS * R, c->stream));
     }
     HIPCHK(c, hipMemsetAsync(P.ctr, 0, 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(P.tile_count, 0, 8, c->stream));
     HIPCHK(c, hipMemsetAsync(P.status, 0, 4, c->stream));
     HIPCHK(c, hipMemsetAsync(P.phi, 0, (size_t)3 * N * R, c->stream));
     // reference volumes V0 from the initial mesh (same FP64 sum as the penalty)
-    HIPCHK(c, launch_tri_sums(P, is_f64(c), c->stream));
+    HIPCHK(c, launch_tri(P, is_f64(c), c->stream));
     HIPCHK(c, launch_set_v0(P, is_f64(c), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
 
@@ -936,7 +945,7 @@ iblb_status iblb_compute_forces(iblb_ctx *c, int32_t d, double *phi_out) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (d < 0 || d >= c->P.n_drops || !phi_out) return set_err(c, IBLB_E_INVAL, "bad droplet or output");
     const bool f64 = is_f64(c);
-    if (c->plan.any_kvol) HIPCHK(c, launch_tri_sums(c->P, f64, c->stream));
+    HIPCHK(c, launch_tri(c->P, f64, c->stream));
     HIPCHK(c, launch_node(c->P, f64, 1, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const DropHost &H = c->plan.drops[d];
@@ -956,7 +965,7 @@ iblb_status iblb_compute_spread(iblb_ctx *c, int32_t b, double *F_out, uint8_t *
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (b < 0 || b >= c->P.n_boxes || (!F_out && !flags_out)) return set_err(c, IBLB_E_INVAL, "bad box or outputs");
     const bool f64 = is_f64(c);
-    if (c->plan.any_kvol) HIPCHK(c, launch_tri_sums(c->P, f64, c->stream));
+    HIPCHK(c, launch_tri(c->P, f64, c->stream));
     HIPCHK(c, launch_node(c->P, f64, 0, c->stream));
     HIPCHK(c, launch_spread(c->P, f64, c->stream));
     HIPCHK(c, launch_epoch(c->P, c->stream));
@@ -1013,6 +1022,7 @@ iblb_status iblb_interpolate(iblb_ctx *c, int32_t d, const double *u_in, double 
     HIPCHK(c, hipMemcpy(c->ws + H.off_u, ub.data(), ub.size(), hipMemcpyHostToDevice));
     const bool f64 = is_f64(c);
     double *Udev = (double *)(c->ws + c->plan.off_uout);
+    HIPCHK(c, launch_tri(c->P, f64, c->stream));
     HIPCHK(c, launch_node(c->P, f64, 1, c->stream));
     HIPCHK(c, launch_interp(c->P, f64, 1, Udev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1026,6 +1036,7 @@ iblb_status iblb_interpolate(iblb_ctx *c, int32_t d, const double *u_in, double 
 iblb_status iblb_read_bins(iblb_ctx *c, int32_t d, int32_t *base_out) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (d < 0 || d >= c->P.n_drops || !base_out) return set_err(c, IBLB_E_INVAL, "bad droplet or output");
+    HIPCHK(c, launch_tri(c->P, is_f64(c), c->stream));
     HIPCHK(c, launch_node(c->P, is_f64(c), 1, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const DropHost &H = c->plan.drops[d];

@@ -22,6 +22,8 @@ constexpr int TILE = 4;
 constexpr int TILE_CELLS = 64;
 constexpr int NB = 64;           // nodes per block
 constexpr int TRI_CHUNK = 256;   // triangles per FP64 partial-sum chunk
+constexpr int TREC = 16;
+constexpr int K1_MAX_THREADS = 256; // launch bound of the stream-collide kernel         // per-triangle record: A, n(3), N/6(3), 3 corner forces(9)
 
 // Velocity set in the library's order: 0 = rest, i and i+9 opposite (i=1..9).
 __host__ __device__ constexpr int cx_of(int i) {
@@ -85,6 +87,9 @@ struct DevPtrs {
     // node arrays, SoA [3][Ntot] unless stated
     void *qh, *ql;              // position, high and low parts (Real)
     void *phi;                  // nodal force (Real)
+    void *trec;                 // [TREC][Ttot] per-triangle records (Real)
+    int32_t *tile_list;         // stamped tiles of the current epoch (global ids)
+    int32_t *tile_count;        // [2] list lengths, indexed by epoch parity
     void *wgt;                  // [12][Ntot] Peskin weights x0..3,y0..3,z0..3 (Real)
     int32_t *base;              // floor(q - 1/2), unwrapped
     int32_t *s0;                // first stencil cell base-1, wrapped where periodic
@@ -111,7 +116,7 @@ struct Launch {
     int grid;                   // stream-collide grid (<= n_rowgroups)
 };
 
-hipError_t launch_tri_sums(const DevPtrs &P, bool f64, hipStream_t s);
+hipError_t launch_tri(const DevPtrs &P, bool f64, hipStream_t s);
 hipError_t launch_set_v0(const DevPtrs &P, bool f64, hipStream_t s);
 hipError_t launch_node(const DevPtrs &P, bool f64, int mode, hipStream_t s);
 hipError_t launch_spread(const DevPtrs &P, bool f64, hipStream_t s);

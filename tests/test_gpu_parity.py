@@ -70,15 +70,21 @@ def test_lattice_steps_match_oracle(storage, zbc, perm):
         s.step(1)
         fg, ug = s.read_state(0, want_u=True)
         fg = to_oracle(fg, perm)
-        tol = 1e-13 if storage == F64 else 2e-6
+        # FP64: the oracle stores full f (~w), so its deviations carry
+        # ~1e-17/5e-5 = 2e-13 relative rounding of their own
+        tol = 2e-12 if storage == F64 else 2e-6
         assert rel_l2(deviation(fg), deviation(f)) < tol * n, n
         assert rel_l2(ug, u) < (1e-12 if storage == F64 else 2e-6), n
 
 
-@pytest.mark.parametrize("storage,tol", [(F64, 1e-10), (F32, 1e-5)])
+# FP32: in the steady state the same rounding of the population update
+# (ulp of a deviation ~ 2^-24 of it) recurs every step and is integrated over
+# the viscous time H^2/(pi^2 nu) ~ 580 steps; bound ~ (H^2/nu) 2^-24 = 3e-4,
+# observed 2.3e-5.  Tolerance 1e-4.
+@pytest.mark.parametrize("storage,tol", [(F64, 1e-10), (F32, 1e-4)])
 def test_poiseuille_closed_form_gpu(storage, tol):
     say("poiseuille", storage)
-    H, tau, g = 24, 0.8, 1e-6
+    H, tau, g = 24, 0.8, 1e-5
     wl = _empty_box(4, 4, H, 0, tau, (g, 0.0, 0.0))
     s = sim(wl, storage, flags=FULL_U | GRAPH)
     nu = (tau - 0.5) / 3
@@ -190,7 +196,7 @@ def test_observables_match_oracle_on_same_positions(storage):
     for k in ("volume", "area", "z_min", "z_max", "height", "contact_radius", "cx", "cy", "cz"):
         assert abs(drops[0][k] - o[k]) <= 1e-11 * max(1.0, abs(o[k])), k
     assert drops[0]["n_crossings"] == o["n_crossings"]
-    f = s.read_state(0)
+    f = to_oracle(s.read_state(0), lib_to_oracle_perm())
     assert abs(boxes[0]["mass"] - oracle.mass(f)) <= 1e-12 * oracle.mass(f)
     assert abs(boxes[0]["max_u"] - oracle.max_u(f)) <= 1e-9 * max(oracle.max_u(f), 1e-12)
 
@@ -313,3 +319,16 @@ def test_instability_is_reported_and_sticky():
     with pytest.raises(P.IblbError) as e:
         s.step(1)
     assert e.value.code == -6
+
+
+def test_set_launch_rejects_shapes_beyond_the_kernel_bound():
+    import paper_2604_17463_amd as P
+    say("launch shape validation")
+    s = sim(configs.plain_c1(), F32)
+    for bx, by in ((32, 16), (64, 8), (512, 1), (48, 4)):
+        with pytest.raises(P.IblbError) as e:
+            s.set_launch(bx, by)
+        assert e.value.code == -1
+    s.set_launch(64, 4)
+    assert s.get_launch() == (64, 4)
+    s.step(3)
