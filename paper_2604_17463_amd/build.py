@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libiblb.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("iblb_kernels.hip", "iblb_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("iblb_fluid.hip", "iblb_mesh.hip", "iblb_api.hip")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -41,7 +41,7 @@ struct BoxHost {
     int sx = 0, tnx = 0, tny = 0, tnz = 0, n_tiles = 0, tile_base = 0;
     int64_t plane = 0;
     int blk_begin = 0, blk_end = 0;
-    size_t off_f[2] = {0, 0}, off_stamp = 0, off_F = 0, off_u = 0;
+    size_t off_f[2] = {0, 0}, off_stamp = 0, off_F = 0, off_u = 0, off_ufull = 0;
 };
 
 struct Plan {
@@ -55,7 +55,7 @@ struct Plan {
     bool any_kvol = false;
     // workspace offsets
     size_t off_boxes = 0, off_drops = 0, off_qh = 0, off_ql = 0, off_phi = 0, off_wgt = 0,
-           off_trec = 0, off_tile_list = 0, off_tile_count = 0,
+           off_trec = 0, off_tile_list = 0, off_tile_count = 0, off_part = 0, off_breg = 0,
            off_base = 0, off_s0 = 0, off_bbox = 0, off_blk_drop = 0, off_tri = 0,
            off_csr_off = 0, off_csr_ent = 0, off_chunks = 0, off_tri_part = 0, off_rows = 0,
            off_tchunk = 0, off_ctr = 0, off_status = 0, off_obs_part = 0, off_obs_out = 0,
@@ -118,14 +118,27 @@ iblb_status check_mesh(const iblb_droplet &d, int di, std::string *err) {
     return IBLB_OK;
 }
 
-uint64_t spread3(uint64_t v) {
-    v &= 0x1fffff;
-    v = (v | v << 32) & 0x1f00000000ffffULL;
-    v = (v | v << 16) & 0x1f0000ff0000ffULL;
-    v = (v | v << 8) & 0x100f00f00f00f00fULL;
-    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
-    v = (v | v << 2) & 0x1249249249249249ULL;
-    return v;
+void rcb_order(const double *q, int32_t *ids, int n, int nblocks) {
+    if (nblocks <= 1) {
+        std::sort(ids, ids + n);
+        return;
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int k = 0; k < n; ++k)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], q[3 * ids[k] + a]);
+            hi[a] = std::max(hi[a], q[3 * ids[k] + a]);
+        }
+    int ax = 0;
+    for (int a = 1; a < 3; ++a)
+        if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+    std::sort(ids, ids + n, [&](int32_t u, int32_t v) {
+        const double qu = q[3 * u + ax], qv = q[3 * v + ax];
+        return qu < qv || (qu == qv && u < v);
+    });
+    const int nl = nblocks / 2;
+    rcb_order(q, ids, nl * NB, nl);
+    rcb_order(q, ids + nl * NB, n - nl * NB, nblocks - nl);
 }
 
 iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
@@ -229,20 +242,12 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
         H.A = D.sigma * (double)((D.m_exp - 1) * (D.n_exp - 1)) / ((double)(D.n_exp - D.m_exp) * D.xi) *
               (1.0 + std::cos(D.theta_eq));  // Eq. 11
         if (D.k_vol > 0) p.any_kvol = true;
-        // Morton order of the initial positions (1 lu cells) for compact node blocks
-        double mn[3] = {1e300, 1e300, 1e300};
-        for (int j = 0; j < D.n_nodes; ++j)
-            for (int a = 0; a < 3; ++a) mn[a] = std::min(mn[a], D.nodes[3 * j + a]);
-        std::vector<uint64_t> key(D.n_nodes);
-        for (int j = 0; j < D.n_nodes; ++j) {
-            uint64_t k = 0;
-            for (int a = 0; a < 3; ++a)
-                k |= spread3((uint64_t)std::floor(D.nodes[3 * j + a] - mn[a])) << a;
-            key[j] = k;
-        }
+        // compact node blocks: recursive coordinate bisection of the initial
+        // positions into ceil(N/64) parts of 64 (the last one partial),
+        // splitting the longest extent at a multiple of 64 nodes
         H.perm.resize(D.n_nodes);
         std::iota(H.perm.begin(), H.perm.end(), 0);
-        std::stable_sort(H.perm.begin(), H.perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+        rcb_order(D.nodes, H.perm.data(), D.n_nodes, H.n_blocks);
         H.inv.resize(D.n_nodes);
         for (int k = 0; k < D.n_nodes; ++k) H.inv[H.perm[k]] = k;
         double c[3] = {0, 0, 0};
@@ -279,6 +284,7 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
         H.off_stamp = take((size_t)H.n_tiles * 4);
         H.off_F = take((size_t)H.n_tiles * 3 * TILE_CELLS * p.real);
         H.off_u = take((size_t)H.n_tiles * 3 * TILE_CELLS * p.real);
+        if (p.flags & IBLB_FLAG_FULL_U) H.off_ufull = take((size_t)3 * H.plane * p.real);
     }
     p.off_boxes = take(sizeof(BoxDev) * p.boxes.size());
     p.off_drops = take(sizeof(DropDev) * std::max<size_t>(p.drops.size(), 1));
@@ -293,6 +299,8 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
     p.off_base = take(3 * N * 4);
     p.off_s0 = take(3 * N * 4);
     p.off_bbox = take(6 * (size_t)p.nblk * 4);
+    p.off_breg = take((size_t)BREG * p.nblk * 4);
+    p.off_part = take((size_t)3 * MAXP * p.nblk * p.real);
     p.off_blk_drop = take((size_t)p.nblk * 4);
     p.off_tri = take(3 * (size_t)p.Ttot * 4);
     p.off_csr_off = take((N + 1) * 4);
@@ -316,11 +324,14 @@ struct iblb_ctx {
     Plan plan;
     char *ws = nullptr;
     hipStream_t stream = nullptr;
-    hipStream_t capture = nullptr;
+    hipStream_t capture = nullptr;  // origin stream of graph captures
+    hipStream_t ib = nullptr;       // second stream: the mesh chain of a step
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     DevPtrs P{};
     Launch L{};
     int rows_per_group = 1;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][advect first]
+    bool pending = false;  // advection of the last step not yet applied
     int parity = 0;
     int64_t step = 0;
     int32_t epoch = 0;       // host mirror of the device step epoch
@@ -363,44 +374,74 @@ iblb_status upload_rows(iblb_ctx *c) {
     return IBLB_OK;
 }
 
-iblb_status enqueue_step(iblb_ctx *c, hipStream_t s, int parity) {
+// One time step on stream s.  The bulk stream-collide (every cell, body
+// force only) runs on s while the mesh chain runs on the second stream:
+// [advection of the previous step] -> triangle records -> node pass (forces,
+// weights, stamps, partial spread) -> stamped-tile list.  Both join before
+// the band kernel, which gathers the spread force of every stamped tile and
+// redoes the collision of its cells.  The advection of this step is left
+// pending (it only needs this step's band velocities) and runs first in the
+// next step's mesh chain, or in flush().
+iblb_status enqueue_step(iblb_ctx *c, hipStream_t s, int parity, bool advect_first) {
     const bool f64 = is_f64(c);
-    HIPCHK(c, launch_tri(c->P, f64, s));
-    HIPCHK(c, launch_node(c->P, f64, 0, s));
-    HIPCHK(c, launch_spread(c->P, f64, s));
-    HIPCHK(c, launch_stream_collide(c->P, c->plan.storage, parity,
-                                    (c->plan.flags & IBLB_FLAG_FULL_U) ? 1 : 0, (float)c->plan.scale,
-                                    c->L, s));
-    HIPCHK(c, launch_interp(c->P, f64, 0, nullptr, s));
+    const int full_u = (c->plan.flags & IBLB_FLAG_FULL_U) ? 1 : 0;
+    const float scale = (float)c->plan.scale;
+    if (c->plan.nblk == 0) {
+        HIPCHK(c, launch_bulk(c->P, c->plan.storage, parity, full_u, scale, c->L, s));
+        return IBLB_OK;
+    }
+    HIPCHK(c, hipEventRecord(c->ev_fork, s));
+    HIPCHK(c, hipStreamWaitEvent(c->ib, c->ev_fork, 0));
+    if (advect_first) HIPCHK(c, launch_interp(c->P, f64, 0, nullptr, c->ib));
+    HIPCHK(c, launch_tri(c->P, f64, c->ib));
+    HIPCHK(c, launch_node(c->P, f64, 0, c->ib));
+    HIPCHK(c, hipEventRecord(c->ev_join, c->ib));
+    HIPCHK(c, launch_bulk(c->P, c->plan.storage, parity, full_u, scale, c->L, s));
+    HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
+    HIPCHK(c, launch_band(c->P, c->plan.storage, parity, full_u, scale, true, s));
+    return IBLB_OK;
+}
+
+// Apply a pending advection (positions then correspond to the completed
+// steps).  Every call that reads or replaces state starts with it.
+iblb_status flush(iblb_ctx *c) {
+    if (!c->pending) return IBLB_OK;
+    HIPCHK(c, launch_interp(c->P, is_f64(c), 0, nullptr, c->stream));
+    c->pending = false;
+    ++c->epoch;
     return IBLB_OK;
 }
 
 void drop_graphs(iblb_ctx *c) {
-    for (auto &e : c->exec)
-        if (e) {
-            (void)hipGraphExecDestroy(e);
-            e = nullptr;
-        }
+    for (auto &row : c->exec)
+        for (auto &e : row)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
 }
 
 iblb_status build_graphs(iblb_ctx *c) {
     drop_graphs(c);
     if (!(c->plan.flags & IBLB_FLAG_GRAPH)) return IBLB_OK;
     if (!c->capture) HIPCHK(c, hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
-    for (int p = 0; p < 2; ++p) {
-        hipGraph_t g = nullptr;
-        HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-        iblb_status st = enqueue_step(c, c->capture, p);
-        hipError_t e = hipStreamEndCapture(c->capture, &g);
-        if (st != IBLB_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return st;
+    for (int p = 0; p < 2; ++p)
+        for (int a = 0; a < 2; ++a) {
+            hipGraph_t g = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+            iblb_status st = enqueue_step(c, c->capture, p, a == 1);
+            hipError_t e = hipStreamEndCapture(c->capture, &g);
+            if (st != IBLB_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess)
+                return set_err(c, IBLB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&c->exec[p][a], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess)
+                return set_err(c, IBLB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         }
-        if (e != hipSuccess) return set_err(c, IBLB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-        e = hipGraphInstantiate(&c->exec[p], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return set_err(c, IBLB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-    }
     return IBLB_OK;
 }
 
@@ -418,8 +459,8 @@ iblb_status time_k1(iblb_ctx *c, int reps, double *ms) {
     HIPCHK(c, hipEventCreate(&b));
     HIPCHK(c, hipEventRecord(a, c->stream));
     for (int r = 0; r < reps; ++r) {
-        HIPCHK(c, launch_stream_collide(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, c->L,
-                                        c->stream));
+        HIPCHK(c, launch_bulk(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, c->L,
+                              c->stream));
         c->parity ^= 1;
     }
     HIPCHK(c, hipEventRecord(b, c->stream));
@@ -553,6 +594,13 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     }
     c->ws = (char *)dev_workspace;
     c->stream = (hipStream_t)hip_stream;
+    if (hipStreamCreateWithFlags(&c->ib, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        const std::string m = "stream/event creation failed";
+        iblb_destroy(c);
+        return set_err(nullptr, IBLB_E_DEVICE, m);
+    }
     auto at = [&](size_t off) { return (void *)(c->ws + off); };
     DevPtrs &P = c->P;
     P.boxes = (BoxDev *)at(p.off_boxes);
@@ -569,6 +617,8 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     P.base = (int32_t *)at(p.off_base);
     P.s0 = (int32_t *)at(p.off_s0);
     P.bbox = (int32_t *)at(p.off_bbox);
+    P.breg = (int32_t *)at(p.off_breg);
+    P.part = at(p.off_part);
     P.blk_drop = (int32_t *)at(p.off_blk_drop);
     P.tri = (int32_t *)at(p.off_tri);
     P.csr_off = (int32_t *)at(p.off_csr_off);
@@ -612,6 +662,7 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
         D.Fband = at(H.off_F);
         D.uband = at(H.off_u);
         D.stamp = (int32_t *)at(H.off_stamp);
+        D.ufull = (p.flags & IBLB_FLAG_FULL_U) ? at(H.off_ufull) : nullptr;
         D.tau = H.b.tau;
         D.rho0 = H.b.rho0;
         for (int a = 0; a < 3; ++a) D.g[a] = H.b.body_force[a];
@@ -699,6 +750,8 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
         HIPCHK(c, hipMemsetAsync(at(H.off_stamp), 0xff, (size_t)H.n_tiles * 4, c->stream));
         HIPCHK(c, hipMemsetAsync(at(H.off_F), 0, (size_t)H.n_tiles * 3 * TILE_CELLS * R, c->stream));
         HIPCHK(c, hipMemsetAsync(at(H.off_u), 0, (size_t)H.n_tiles * 3 * TILE_CELLS * R, c->stream));
+        if (p.flags & IBLB_FLAG_FULL_U)
+            HIPCHK(c, hipMemsetAsync(at(H.off_ufull), 0, (size_t)3 * H.plane * R, c->stream));
     }
     HIPCHK(c, hipMemsetAsync(P.ctr, 0, 4, c->stream));
     HIPCHK(c, hipMemsetAsync(P.tile_count, 0, 8, c->stream));
@@ -739,17 +792,19 @@ iblb_status iblb_step(iblb_ctx *c, int64_t n) {
     if (n < 0) return set_err(c, IBLB_E_INVAL, "n_steps < 0");
     if (c->unstable) return set_err(c, IBLB_E_STATE, "context is unstable; no further steps");
     for (int64_t k = 0; k < n; ++k) {
-        if (c->exec[c->parity]) {
-            HIPCHK(c, hipGraphLaunch(c->exec[c->parity], c->stream));
+        const int a = c->pending ? 1 : 0;
+        if (c->exec[c->parity][a]) {
+            HIPCHK(c, hipGraphLaunch(c->exec[c->parity][a], c->stream));
         } else {
-            iblb_status st = enqueue_step(c, c->stream, c->parity);
+            iblb_status st = enqueue_step(c, c->stream, c->parity, a == 1);
             if (st != IBLB_OK) return st;
         }
         c->parity ^= 1;
         ++c->step;
         if (c->plan.nblk > 0) {
+            if (a) ++c->epoch;  // the advection at the head of the step
             c->last_step_epoch = c->epoch;
-            ++c->epoch;
+            c->pending = true;
         }
     }
     return IBLB_OK;
@@ -760,6 +815,10 @@ iblb_status iblb_observables(iblb_ctx *c, iblb_obs *per_drop, int32_t n_drops, i
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if ((per_drop && n_drops != c->P.n_drops) || (per_box && n_boxes != c->P.n_boxes))
         return set_err(c, IBLB_E_INVAL, "output counts do not match the configuration");
+    {
+        iblb_status st = flush(c);
+        if (st != IBLB_OK) return st;
+    }
     HIPCHK(c, launch_box_obs(c->P, c->plan.storage, c->parity, (float)(1.0 / c->plan.scale), c->stream));
     HIPCHK(c, launch_drop_obs(c->P, is_f64(c), c->stream));
     const size_t nobs = (size_t)c->P.n_drops * OBS_DROP + (size_t)c->P.n_boxes * OBS_BOX;
@@ -805,6 +864,10 @@ iblb_status iblb_observables(iblb_ctx *c, iblb_obs *per_drop, int32_t n_drops, i
 iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_out) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (box < 0 || box >= c->P.n_boxes || (!f_out && !u_out)) return set_err(c, IBLB_E_INVAL, "bad box or outputs");
+    {
+        iblb_status fst = flush(c);
+        if (fst != IBLB_OK) return fst;
+    }
     const BoxHost &H = c->plan.boxes[box];
     const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz;
     const size_t cells = (size_t)nx * ny * nz;
@@ -831,20 +894,31 @@ iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_o
                     }
                 }
     }
-    if (u_out) {
+    if (u_out && (c->plan.flags & IBLB_FLAG_FULL_U)) {
+        const int R = c->plan.real;
+        std::vector<char> uf((size_t)3 * H.plane * R);
+        HIPCHK(c, hipMemcpy(uf.data(), c->ws + H.off_ufull, uf.size(), hipMemcpyDeviceToHost));
+        for (int a = 0; a < 3; ++a)
+            for (int z = 0; z < nz; ++z)
+                for (int y = 0; y < ny; ++y)
+                    for (int x = 0; x < nx; ++x) {
+                        const size_t k = (size_t)a * H.plane + ((size_t)z * ny + y) * H.sx + x;
+                        const double v = R == 8 ? ((double *)uf.data())[k] : ((float *)uf.data())[k];
+                        u_out[(size_t)a * cells + ((size_t)z * ny + y) * nx + x] = c->step > 0 ? v : NAN;
+                    }
+    } else if (u_out) {
         const int R = c->plan.real;
         std::vector<char> ub((size_t)H.n_tiles * 3 * TILE_CELLS * R);
         std::vector<int32_t> stamp(H.n_tiles);
         HIPCHK(c, hipMemcpy(ub.data(), c->ws + H.off_u, ub.size(), hipMemcpyDeviceToHost));
         HIPCHK(c, hipMemcpy(stamp.data(), c->ws + H.off_stamp, stamp.size() * 4, hipMemcpyDeviceToHost));
-        const bool all = (c->plan.flags & IBLB_FLAG_FULL_U) && c->step > 0;
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
                     const size_t cell = ((size_t)z * ny + y) * nx + x;
                     const size_t tile = ((size_t)(z >> 2) * H.tny + (y >> 2)) * H.tnx + (x >> 2);
                     const int loc = ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
-                    const bool ok = all || (c->last_step_epoch >= 0 && stamp[tile] == c->last_step_epoch);
+                    const bool ok = c->last_step_epoch >= 0 && stamp[tile] == c->last_step_epoch;
                     for (int a = 0; a < 3; ++a) {
                         const size_t k = (tile * 3 + a) * TILE_CELLS + loc;
                         const double v = R == 8 ? ((const double *)ub.data())[k] : ((const float *)ub.data())[k];
@@ -858,6 +932,10 @@ iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_o
 iblb_status iblb_write_state(iblb_ctx *c, int32_t box, const double *f_in) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (box < 0 || box >= c->P.n_boxes || !f_in) return set_err(c, IBLB_E_INVAL, "bad box or input");
+    {
+        iblb_status fst = flush(c);
+        if (fst != IBLB_OK) return fst;
+    }
     const BoxHost &H = c->plan.boxes[box];
     const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz;
     const size_t cells = (size_t)nx * ny * nz;
@@ -891,6 +969,10 @@ iblb_status iblb_write_state(iblb_ctx *c, int32_t box, const double *f_in) {
 iblb_status iblb_read_nodes(iblb_ctx *c, int32_t d, double *nodes_out) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (d < 0 || d >= c->P.n_drops || !nodes_out) return set_err(c, IBLB_E_INVAL, "bad droplet or output");
+    {
+        iblb_status fst = flush(c);
+        if (fst != IBLB_OK) return fst;
+    }
     const DropHost &H = c->plan.drops[d];
     const int N = c->P.Ntot, R = c->plan.real;
     std::vector<char> qh((size_t)3 * N * R), ql((size_t)3 * N * R);
@@ -910,6 +992,10 @@ iblb_status iblb_read_nodes(iblb_ctx *c, int32_t d, double *nodes_out) {
 iblb_status iblb_write_nodes(iblb_ctx *c, int32_t d, const double *nodes_in) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (d < 0 || d >= c->P.n_drops || !nodes_in) return set_err(c, IBLB_E_INVAL, "bad droplet or input");
+    {
+        iblb_status fst = flush(c);
+        if (fst != IBLB_OK) return fst;
+    }
     const DropHost &H = c->plan.drops[d];
     const iblb_box &B = c->plan.boxes[H.d.box].b;
     for (int k = 0; k < 3 * H.d.n_nodes; ++k)
@@ -944,6 +1030,10 @@ iblb_status iblb_write_nodes(iblb_ctx *c, int32_t d, const double *nodes_in) {
 iblb_status iblb_compute_forces(iblb_ctx *c, int32_t d, double *phi_out) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (d < 0 || d >= c->P.n_drops || !phi_out) return set_err(c, IBLB_E_INVAL, "bad droplet or output");
+    {
+        iblb_status fst = flush(c);
+        if (fst != IBLB_OK) return fst;
+    }
     const bool f64 = is_f64(c);
     HIPCHK(c, launch_tri(c->P, f64, c->stream));
     HIPCHK(c, launch_node(c->P, f64, 1, c->stream));
@@ -964,10 +1054,14 @@ iblb_status iblb_compute_forces(iblb_ctx *c, int32_t d, double *phi_out) {
 iblb_status iblb_compute_spread(iblb_ctx *c, int32_t b, double *F_out, uint8_t *flags_out) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (b < 0 || b >= c->P.n_boxes || (!F_out && !flags_out)) return set_err(c, IBLB_E_INVAL, "bad box or outputs");
+    {
+        iblb_status fst = flush(c);
+        if (fst != IBLB_OK) return fst;
+    }
     const bool f64 = is_f64(c);
     HIPCHK(c, launch_tri(c->P, f64, c->stream));
     HIPCHK(c, launch_node(c->P, f64, 0, c->stream));
-    HIPCHK(c, launch_spread(c->P, f64, c->stream));
+    HIPCHK(c, launch_band(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, false, c->stream));
     HIPCHK(c, launch_epoch(c->P, c->stream));
     const int32_t used = c->epoch;
     ++c->epoch;
@@ -1001,6 +1095,10 @@ iblb_status iblb_compute_spread(iblb_ctx *c, int32_t b, double *F_out, uint8_t *
 iblb_status iblb_interpolate(iblb_ctx *c, int32_t d, const double *u_in, double *U_out) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (d < 0 || d >= c->P.n_drops || !u_in || !U_out) return set_err(c, IBLB_E_INVAL, "bad droplet or arrays");
+    {
+        iblb_status fst = flush(c);
+        if (fst != IBLB_OK) return fst;
+    }
     const DropHost &Dh = c->plan.drops[d];
     const BoxHost &H = c->plan.boxes[Dh.d.box];
     const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz, R = c->plan.real;
@@ -1036,6 +1134,10 @@ iblb_status iblb_interpolate(iblb_ctx *c, int32_t d, const double *u_in, double 
 iblb_status iblb_read_bins(iblb_ctx *c, int32_t d, int32_t *base_out) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (d < 0 || d >= c->P.n_drops || !base_out) return set_err(c, IBLB_E_INVAL, "bad droplet or output");
+    {
+        iblb_status fst = flush(c);
+        if (fst != IBLB_OK) return fst;
+    }
     HIPCHK(c, launch_tri(c->P, is_f64(c), c->stream));
     HIPCHK(c, launch_node(c->P, is_f64(c), 1, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1104,6 +1206,9 @@ iblb_status iblb_destroy(iblb_ctx *c) {
     if (!c) return IBLB_OK;
     drop_graphs(c);
     if (c->capture) (void)hipStreamDestroy(c->capture);
+    if (c->ib) (void)hipStreamDestroy(c->ib);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->host_obs) (void)hipHostFree(c->host_obs);
     if (c->host_status) (void)hipHostFree(c->host_status);
     delete c;

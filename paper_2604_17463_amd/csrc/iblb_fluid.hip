@@ -1,0 +1,379 @@
+// Fluid kernels of the IBLB wetting step (gfx950): the bulk fused
+// pull-stream / moments / BGK-Guo collision over every cell with the body
+// force only, the band kernel that gathers the spread interface force for
+// each stamped 4x4x4 tile and redoes the collision of its 64 cells with it,
+// and the per-box observables.
+#include "iblb_device.h"
+
+namespace iblb {
+
+// ------------------------------------------------------------------- bulk
+// Every cell of every box, F = body force.  A workgroup takes whole x-rows
+// (a row group); threads stride along x so the +-1 shifted loads of a row
+// stay inside one workgroup.  UROW: each wavefront lies in one row
+// (threads_x a multiple of 64), so the row addressing is wave-uniform and
+// lives in scalar registers.  Cells next to a mesh are recomputed by the
+// band kernel afterwards.
+template <int ST, bool UROW>
+__global__ void __launch_bounds__(K1_MAX_THREADS)
+    k_bulk(DevPtrs P, int parity, int full_u, float scale, float inv) {
+    using S = Stor<ST>;
+    using R = typename S::R;
+    constexpr uint32_t EB = sizeof(typename S::T);
+    const int tx = threadIdx.x, ty = threadIdx.y, BX = blockDim.x, BY = blockDim.y;
+    const IBLB_CONST RowGroup *rows = (const IBLB_CONST RowGroup *)P.rows;
+    for (int gi = blockIdx.x; gi < P.n_rowgroups; gi += gridDim.x) {
+        const IBLB_CONST RowGroup &rg = rows[gi];
+        const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + rg.box;
+        const int nx = B->nx, ny = B->ny, nz = B->nz, sx = B->sx;
+        const bool zper = B->zbc == 1;
+        const uint64_t pb = (uint64_t)B->plane * EB;
+        const IBLB_GLOBAL char *__restrict__ src = (const IBLB_GLOBAL char *)B->f[parity];
+        IBLB_GLOBAL char *__restrict__ dst = (IBLB_GLOBAL char *)B->f[parity ^ 1];
+        const R omega = (R)B->omega, guo = (R)B->guo, rho0 = (R)B->rho0;
+        const R gx = (R)B->g[0], gy = (R)B->g[1], gz = (R)B->g[2];
+        IBLB_GLOBAL R *__restrict__ uf = (IBLB_GLOBAL R *)B->ufull;
+        const uint64_t plane = (uint64_t)B->plane;
+        for (int r0 = rg.r0 + ty; r0 < rg.r1; r0 += BY) {
+            const int r = UROW ? __builtin_amdgcn_readfirstlane(r0) : r0;
+            const int z = r / ny, y = r - z * ny;
+            const RowAddr ra = row_addr(y, z, ny, nz, sx, zper, EB);
+            for (int x = tx; x < nx; x += BX) {
+                R g[Q], u[3], rho;
+                pull<ST>(src, pb, ra, x, nx, inv, g);
+                const uint32_t own = ra.ro[1][1] + (uint32_t)x * EB;
+                collide_store<ST>(g, gx, gy, gz, rho0, omega, guo, dst, pb, own, scale, u, rho);
+                if (full_u) {
+                    const uint64_t e = own / EB;
+                    uf[e] = u[0];
+                    uf[plane + e] = u[1];
+                    uf[2 * plane + e] = u[2];
+                }
+                if (!(rho > R(0) && rho < R(FLT_MAX))) atomicOr(P.status, BIT_RHO);
+                if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > R(1) / R(3)) atomicOr(P.status, BIT_MACH);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ spread gather
+// Spread force density (Eq. 8) at cell (cx,cy,cz) of the tile [x0..x1] x
+// [y0..y1] x [z0..z1], for the calling lane.  Node blocks whose stencil box
+// meets the tile contribute in ascending block order; a block's own
+// contribution is the partial sum its node pass accumulated over its nodes
+// in ascending order (read from the block's partial region), or, for a
+// block whose region did not fit, the nodes summed here one by one in the
+// same order.  No atomics: the sum order per cell is fixed.
+template <typename R>
+__device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxDev *B, int x0, int x1,
+                                         int y0, int y1, int z0, int z1, int cx, int cy, int cz,
+                                         R &F0, R &F1, R &F2) {
+    const int lane = threadIdx.x & 63;
+    const int nb = P.nblk, N = P.Ntot;
+    const bool zper = B->zbc == 1;
+    const int nx = B->nx, ny = B->ny, nz = B->nz;
+    const IBLB_GLOBAL R *part = (const IBLB_GLOBAL R *)P.part;
+    const IBLB_CONST int32_t *breg = (const IBLB_CONST int32_t *)P.breg;
+    for (int kb = B->blk_begin; kb < B->blk_end; kb += 64) {
+        const int mb = kb + lane;
+        bool hit = false;
+        if (mb < B->blk_end)
+            hit = meets(P.bbox[0 * nb + mb], P.bbox[1 * nb + mb], x0, x1, nx, true) &&
+                  meets(P.bbox[2 * nb + mb], P.bbox[3 * nb + mb], y0, y1, ny, true) &&
+                  meets(P.bbox[4 * nb + mb], P.bbox[5 * nb + mb], z0, z1, nz, zper);
+        uint64_t bmask = __ballot(hit);
+        while (bmask) {
+            // up to four candidate blocks per round: their loads are issued
+            // together, their sums added in block order
+            int ids[4], n = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (bmask) {
+                    ids[n++] = kb + __builtin_ctzll(bmask);
+                    bmask &= bmask - 1;
+                }
+            R v[4][3];
+            bool ovf[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[k][0] = v[k][1] = v[k][2] = R(0);
+                ovf[k] = false;
+                if (k < n) {
+                    const IBLB_CONST int32_t *br = breg + (int64_t)ids[k] * BREG;
+                    ovf[k] = br[6] != 0;
+                    if (!ovf[k]) {
+                        int dx = cx - br[0], dy = cy - br[1], dz = cz - br[2];
+                        if (dx < 0) dx += nx;
+                        if (dy < 0) dy += ny;
+                        if (zper && dz < 0) dz += nz;
+                        const int ex = br[3], ey = br[4], ez = br[5];
+                        if (dx < ex && dy < ey && dz >= 0 && dz < ez) {
+                            const int64_t c = (int64_t)ids[k] * 3 * MAXP + (dz * ey + dy) * ex + dx;
+                            v[k][0] = part[c];
+                            v[k][1] = part[c + MAXP];
+                            v[k][2] = part[c + 2 * MAXP];
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (k >= n) break;
+                if (!ovf[k]) {
+                    F0 += v[k][0];
+                    F1 += v[k][1];
+                    F2 += v[k][2];
+                    continue;
+                }
+                // block without a partial region: its nodes one by one
+                const int blk = ids[k];
+                const DropDev &D = P.drops[P.blk_drop[blk]];
+                const int j = blk * NB + lane;
+                bool nh = false;
+                if (j - D.node_off < D.n_nodes) {
+                    const int bx = P.base[j], by = P.base[N + j], bz = P.base[2 * N + j];
+                    nh = meets(bx - 1, bx + 2, x0, x1, nx, true) &&
+                         meets(by - 1, by + 2, y0, y1, ny, true) &&
+                         meets(bz - 1, bz + 2, z0, z1, nz, zper);
+                }
+                uint64_t nmask = __ballot(nh);
+                if (!nmask) continue;
+                const R *wgt = (const R *)P.wgt, *phi = (const R *)P.phi;
+                int s0x = 0, s0y = 0, s0z = 0;
+                R w[12], f[3];
+#pragma unroll
+                for (int q = 0; q < 12; ++q) w[q] = 0;
+                f[0] = f[1] = f[2] = 0;
+                if (nh) {
+                    s0x = P.s0[j];
+                    s0y = P.s0[N + j];
+                    s0z = P.s0[2 * N + j];
+#pragma unroll
+                    for (int q = 0; q < 12; ++q) w[q] = wgt[q * N + j];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) f[q] = phi[q * N + j];
+                }
+                while (nmask) {
+                    const int nl = __builtin_ctzll(nmask);
+                    nmask &= nmask - 1;
+                    int ox = cx - bcast_i(s0x, nl), oy = cy - bcast_i(s0y, nl), oz = cz - bcast_i(s0z, nl);
+                    if (ox < 0) ox += nx;
+                    if (oy < 0) oy += ny;
+                    if (zper && oz < 0) oz += nz;
+                    const R ax = pick4(ox, bcast(w[0], nl), bcast(w[1], nl), bcast(w[2], nl), bcast(w[3], nl));
+                    const R ay = pick4(oy, bcast(w[4], nl), bcast(w[5], nl), bcast(w[6], nl), bcast(w[7], nl));
+                    const R az = pick4(oz, bcast(w[8], nl), bcast(w[9], nl), bcast(w[10], nl), bcast(w[11], nl));
+                    const R wv = ax * ay * az;
+                    F0 += bcast(f[0], nl) * wv;
+                    F1 += bcast(f[1], nl) * wv;
+                    F2 += bcast(f[2], nl) * wv;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------- band
+// One wavefront per stamped tile of this epoch, one lane per cell: gather
+// the spread force, then (COLLIDE) pull, collide with F = body force +
+// spread force, store the populations over the bulk result and write u to
+// the band; or (!COLLIDE, inspection) store F in the band.
+template <int ST, bool COLLIDE>
+__global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u, float scale, float inv) {
+    using S = Stor<ST>;
+    using R = typename S::R;
+    constexpr uint32_t EB = sizeof(typename S::T);
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * 4;
+    const int ctr = *P.ctr;
+    const int count = P.tile_count[ctr & 1];
+    for (int i = wave; i < count; i += nwaves) {
+        const int gt = P.tile_list[i];
+        const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + P.tchunk_box[gt / TILE_CELLS];
+        const int lt = gt - B->tile_base;
+        const int tx = lt % B->tnx, ty = (lt / B->tnx) % B->tny, tz = lt / (B->tnx * B->tny);
+        const int x0 = tx * TILE, y0 = ty * TILE, z0 = tz * TILE;
+        const int x1 = min(x0 + TILE - 1, B->nx - 1), y1 = min(y0 + TILE - 1, B->ny - 1),
+                  z1 = min(z0 + TILE - 1, B->nz - 1);
+        const int cx = x0 + (lane & 3), cy = y0 + ((lane >> 2) & 3), cz = z0 + (lane >> 4);
+        R F0 = 0, F1 = 0, F2 = 0;
+        gather_F<R>(P, B, x0, x1, y0, y1, z0, z1, cx, cy, cz, F0, F1, F2);
+        if (!COLLIDE) {
+            IBLB_GLOBAL R *Fb = (IBLB_GLOBAL R *)B->Fband + (int64_t)lt * 3 * TILE_CELLS;
+            Fb[lane] = F0;
+            Fb[TILE_CELLS + lane] = F1;
+            Fb[2 * TILE_CELLS + lane] = F2;
+            continue;
+        }
+        if (cx >= B->nx || cy >= B->ny || cz >= B->nz) continue;
+        const uint64_t pb = (uint64_t)B->plane * EB;
+        const IBLB_GLOBAL char *src = (const IBLB_GLOBAL char *)B->f[parity];
+        IBLB_GLOBAL char *dst = (IBLB_GLOBAL char *)B->f[parity ^ 1];
+        const RowAddr ra = row_addr(cy, cz, B->ny, B->nz, B->sx, B->zbc == 1, EB);
+        R g[Q], u[3], rho;
+        pull<ST>(src, pb, ra, cx, B->nx, inv, g);
+        const uint32_t own = ra.ro[1][1] + (uint32_t)cx * EB;
+        collide_store<ST>(g, (R)B->g[0] + F0, (R)B->g[1] + F1, (R)B->g[2] + F2, (R)B->rho0,
+                          (R)B->omega, (R)B->guo, dst, pb, own, scale, u, rho);
+        IBLB_GLOBAL R *ub = (IBLB_GLOBAL R *)B->uband + (int64_t)lt * 3 * TILE_CELLS;
+        ub[lane] = u[0];
+        ub[TILE_CELLS + lane] = u[1];
+        ub[2 * TILE_CELLS + lane] = u[2];
+        if (full_u) {
+            IBLB_GLOBAL R *uf = (IBLB_GLOBAL R *)B->ufull;
+            const uint64_t e = own / EB, plane = (uint64_t)B->plane;
+            uf[e] = u[0];
+            uf[plane + e] = u[1];
+            uf[2 * plane + e] = u[2];
+        }
+        if (!(rho > R(0) && rho < R(FLT_MAX))) atomicOr(P.status, BIT_RHO);
+        if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > R(1) / R(3)) atomicOr(P.status, BIT_MACH);
+    }
+}
+
+// ------------------------------------------------------------ observables
+__device__ __forceinline__ double block_sum256(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ double block_max256(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Mass and largest bare velocity of one box's current populations: fixed
+// partition of the rows over OBS_GROUPS workgroups, then a fixed-order
+// final sum.
+template <int ST>
+__global__ void __launch_bounds__(256) k_box_obs(DevPtrs P, int box, int parity, float inv) {
+    using S = Stor<ST>;
+    using R = typename S::R;
+    __shared__ double sh[256];
+    const BoxDev &B = P.boxes[box];
+    const int rows = B.ny * B.nz;
+    const int r0 = (int)((int64_t)rows * blockIdx.x / gridDim.x);
+    const int r1 = (int)((int64_t)rows * (blockIdx.x + 1) / gridDim.x);
+    const IBLB_GLOBAL char *src = (const IBLB_GLOBAL char *)B.f[parity];
+    const uint64_t pb = (uint64_t)B.plane * sizeof(typename S::T);
+    double m = 0.0, umax = 0.0;
+    for (int r = r0; r < r1; ++r) {
+        const int z = r / B.ny, y = r - z * B.ny;
+        const RowAddr ra = row_addr(y, z, B.ny, B.nz, B.sx, B.zbc == 1, sizeof(typename S::T));
+        for (int x = threadIdx.x; x < B.nx; x += 256) {
+            R g[Q];
+            pull<ST>(src, pb, ra, x, B.nx, inv, g);
+            double dr = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                dr += (double)g[i];
+                jx += cx_of(i) * (double)g[i];
+                jy += cy_of(i) * (double)g[i];
+                jz += cz_of(i) * (double)g[i];
+            }
+            m += dr;
+            umax = fmax(umax, sqrt(jx * jx + jy * jy + jz * jz) / (B.rho0 + dr));
+        }
+    }
+    m = block_sum256(m, sh);
+    umax = block_max256(umax, sh);
+    if (threadIdx.x == 0) {
+        P.obs_part[2 * blockIdx.x] = m;
+        P.obs_part[2 * blockIdx.x + 1] = umax;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_box_obs_final(DevPtrs P, int box, int groups) {
+    __shared__ double sh[256];
+    double m = 0.0, umax = 0.0;
+    for (int k = threadIdx.x; k < groups; k += 256) {
+        m += P.obs_part[2 * k];
+        umax = fmax(umax, P.obs_part[2 * k + 1]);
+    }
+    m = block_sum256(m, sh);
+    umax = block_max256(umax, sh);
+    if (threadIdx.x == 0) {
+        double *o = P.obs_out + P.n_drops * OBS_DROP + box * OBS_BOX;
+        o[0] = P.boxes[box].cells_rho0 + m;
+        o[1] = umax;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int ST>
+static hipError_t launch_bulk_t(const DevPtrs &P, int parity, int full_u, float scale, const Launch &L,
+                                hipStream_t s) {
+    // never launch a shape the kernel was not compiled for
+    if (L.bx < 1 || L.by < 1 || L.bx * L.by > K1_MAX_THREADS || L.grid < 1) return hipErrorInvalidValue;
+    const dim3 block(L.bx, L.by), grid(L.grid);
+    const float inv = 1.0f / scale;
+    if (L.bx % 64 == 0)
+        hipLaunchKernelGGL((k_bulk<ST, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    else
+        hipLaunchKernelGGL((k_bulk<ST, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_bulk(const DevPtrs &P, int storage, int parity, int full_u, float scale,
+                       const Launch &L, hipStream_t s) {
+    switch (storage) {
+    case 0: return launch_bulk_t<0>(P, parity, full_u, scale, L, s);
+    case 1: return launch_bulk_t<1>(P, parity, full_u, scale, L, s);
+    case 2: return launch_bulk_t<2>(P, parity, full_u, scale, L, s);
+    default: return launch_bulk_t<3>(P, parity, full_u, scale, L, s);
+    }
+}
+
+template <int ST, bool C>
+static void launch_band_t(const DevPtrs &P, int parity, int full_u, float scale, hipStream_t s) {
+    const int grid = min((P.total_tiles + 3) / 4, 2048);
+    hipLaunchKernelGGL((k_band<ST, C>), dim3(grid), dim3(256), 0, s, P, parity, full_u, scale, 1.0f / scale);
+}
+
+hipError_t launch_band(const DevPtrs &P, int storage, int parity, int full_u, float scale, bool collide,
+                       hipStream_t s) {
+    if (P.nblk == 0 || P.total_tiles == 0) return hipSuccess;
+    if (collide) {
+        switch (storage) {
+        case 0: launch_band_t<0, true>(P, parity, full_u, scale, s); break;
+        case 1: launch_band_t<1, true>(P, parity, full_u, scale, s); break;
+        case 2: launch_band_t<2, true>(P, parity, full_u, scale, s); break;
+        default: launch_band_t<3, true>(P, parity, full_u, scale, s); break;
+        }
+    } else if (storage == 0) {
+        launch_band_t<0, false>(P, parity, full_u, scale, s);
+    } else {
+        launch_band_t<1, false>(P, parity, full_u, scale, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_box_obs(const DevPtrs &P, int storage, int parity, float inv, hipStream_t s) {
+    for (int b = 0; b < P.n_boxes; ++b) {
+        const dim3 grid(OBS_GROUPS), block(256);
+        switch (storage) {
+        case 0: hipLaunchKernelGGL(k_box_obs<0>, grid, block, 0, s, P, b, parity, inv); break;
+        case 1: hipLaunchKernelGGL(k_box_obs<1>, grid, block, 0, s, P, b, parity, inv); break;
+        case 2: hipLaunchKernelGGL(k_box_obs<2>, grid, block, 0, s, P, b, parity, inv); break;
+        default: hipLaunchKernelGGL(k_box_obs<3>, grid, block, 0, s, P, b, parity, inv); break;
+        }
+        hipLaunchKernelGGL(k_box_obs_final, dim3(1), dim3(256), 0, s, P, b, OBS_GROUPS);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace iblb

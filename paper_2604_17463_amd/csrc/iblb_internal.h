@@ -6,11 +6,11 @@
 //     f_i - w_i rho0 (scaled for FP16); a buffer holds the post-collision
 //     populations of the last step and the next step pulls from it;
 //   - 4x4x4 tiles (64 cells = one wavefront): an epoch stamp per tile and,
-//     in tile-major order [tile][3][64], the spread force F and the velocity
-//     u written by the stream-collide kernel in stamped tiles.
-// Per droplet, nodes are renumbered once (Morton order of the initial
-// positions) and grouped in blocks of 64 (one wavefront), padded per
-// droplet.  Node arrays are SoA over the padded global node index.
+//     in tile-major order [tile][3][64], the velocity u written by the band
+//     kernel in stamped tiles (and the spread force F for inspection).
+// Per droplet, nodes are renumbered once (recursive coordinate bisection of
+// the initial positions) into compact blocks of 64 (one wavefront), padded
+// per droplet.  Node arrays are SoA over the padded global node index.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -23,7 +23,9 @@ constexpr int TILE_CELLS = 64;
 constexpr int NB = 64;           // nodes per block
 constexpr int TRI_CHUNK = 256;   // triangles per FP64 partial-sum chunk
 constexpr int TREC = 16;
-constexpr int K1_MAX_THREADS = 256; // launch bound of the stream-collide kernel         // per-triangle record: A, n(3), N/6(3), 3 corner forces(9)
+constexpr int K1_MAX_THREADS = 256; // launch bound of the bulk stream-collide kernel
+constexpr int MAXP = 2048;          // cells of a node block's partial-spread region
+constexpr int BREG = 8;             // ints per block region descriptor         // per-triangle record: A, n(3), N/6(3), 3 corner forces(9)
 
 // Velocity set in the library's order: 0 = rest, i and i+9 opposite (i=1..9).
 __host__ __device__ constexpr int cx_of(int i) {
@@ -58,6 +60,7 @@ struct BoxDev {
     int32_t blk_begin, blk_end; // node blocks of the box's droplets
     void *f[2];                 // population buffers
     void *Fband, *uband;        // [n_tiles][3][64] of Real
+    void *ufull;                // [3][plane] u of every cell (testing mode) or null
     int32_t *stamp;             // [n_tiles]
     double tau, rho0, g[3];
     double omega, guo;          // 1/tau, 1 - 1/(2 tau)
@@ -94,6 +97,8 @@ struct DevPtrs {
     int32_t *base;              // floor(q - 1/2), unwrapped
     int32_t *s0;                // first stencil cell base-1, wrapped where periodic
     int32_t *bbox;              // [6][nblk]: x0,x1,y0,y1,z0,z1 of stencil cells
+    int32_t *breg;              // [nblk][BREG]: partial region x0,y0,z0 (wrapped), ex,ey,ez, overflow
+    void *part;                 // [nblk][3][MAXP] partial spread regions (Real)
     int32_t *blk_drop;          // [nblk]
     int32_t *tri;               // [Ttot][3] global node ids
     int32_t *csr_off;           // [Ntot+1]
@@ -112,16 +117,17 @@ struct DevPtrs {
 
 // Launch entry points implemented in iblb_kernels.hip.
 struct Launch {
-    int bx, by;                 // stream-collide block shape
-    int grid;                   // stream-collide grid (<= n_rowgroups)
+    int bx, by;                 // bulk stream-collide block shape
+    int grid;                   // bulk stream-collide grid (<= n_rowgroups)
 };
 
 hipError_t launch_tri(const DevPtrs &P, bool f64, hipStream_t s);
 hipError_t launch_set_v0(const DevPtrs &P, bool f64, hipStream_t s);
 hipError_t launch_node(const DevPtrs &P, bool f64, int mode, hipStream_t s);
-hipError_t launch_spread(const DevPtrs &P, bool f64, hipStream_t s);
-hipError_t launch_stream_collide(const DevPtrs &P, int storage, int parity, int full_u,
-                                 float scale, const Launch &L, hipStream_t s);
+hipError_t launch_bulk(const DevPtrs &P, int storage, int parity, int full_u, float scale,
+                       const Launch &L, hipStream_t s);
+hipError_t launch_band(const DevPtrs &P, int storage, int parity, int full_u, float scale,
+                       bool collide, hipStream_t s);
 hipError_t launch_interp(const DevPtrs &P, bool f64, int mode, double *Uout, hipStream_t s);
 hipError_t launch_epoch(const DevPtrs &P, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);

@@ -1,0 +1,620 @@
+// Mesh kernels of the IBLB wetting step (gfx950): per-triangle records,
+// the node pass (interface forces, Peskin weights, tile stamps and the
+// block-partial spread), the stamped-tile list, interpolation with forward
+// Euler advection, and the per-droplet observables.
+#include "iblb_device.h"
+
+namespace iblb {
+
+// ------------------------------------------------------- per-triangle pass
+// One thread per triangle (a,b,c): N = (q_b - q_a) x (q_c - q_a), area
+// A_t = |N|/2, unit normal n_t, the volume-gradient share N/6 and the three
+// corner forces -sigma dA_t/dq = (sigma/2)(q_prev - q_next) x n_t, stored as
+// a record [TREC][Ttot] for the node gather.  Also the FP64 volume
+// sum_t (a-r).((b-r)x(c-r))/6 and area per chunk of 256 triangles
+// (positions relative to the droplet's reference point r), fixed tree.
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_tri(DevPtrs P) {
+    __shared__ double sv[256], sa[256];
+    const TriChunk ch = P.chunks[blockIdx.x];
+    const DropDev &D = P.drops[ch.drop];
+    const R *qh = (const R *)P.qh, *ql = (const R *)P.ql;
+    const int t = ch.t0 + threadIdx.x;
+    const int T = P.Ttot, N = P.Ntot;
+    double v = 0.0, ar = 0.0;
+    if (t < ch.t1) {
+        const Node3<R> a = load_node(qh, ql, N, P.tri[3 * t]);
+        const Node3<R> b = load_node(qh, ql, N, P.tri[3 * t + 1]);
+        const Node3<R> c = load_node(qh, ql, N, P.tri[3 * t + 2]);
+        R e1[3], e2[3], Nt[3], cb[3], ac[3], ba[3], f0[3], f1[3], f2[3];
+        diff(b, a, e1);
+        diff(c, a, e2);
+        cross3(e1, e2, Nt);
+        const R len = sqrt(Nt[0] * Nt[0] + Nt[1] * Nt[1] + Nt[2] * Nt[2]);
+        const R il = R(1) / len;
+        const R nt[3] = {Nt[0] * il, Nt[1] * il, Nt[2] * il};
+        const R hs = R(0.5) * (R)D.sigma;
+        diff(c, b, cb);
+        diff(a, c, ac);
+        diff(b, a, ba);
+        cross3(cb, nt, f0);
+        cross3(ac, nt, f1);
+        cross3(ba, nt, f2);
+        R *tr = (R *)P.trec;
+        tr[0 * T + t] = R(0.5) * len;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            tr[(1 + k) * T + t] = nt[k];
+            tr[(4 + k) * T + t] = Nt[k] / R(6);
+            tr[(7 + k) * T + t] = hs * f0[k];
+            tr[(10 + k) * T + t] = hs * f1[k];
+            tr[(13 + k) * T + t] = hs * f2[k];
+        }
+        double p[3][3];
+        const Node3<R> *abc[3] = {&a, &b, &c};
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                p[cc][k] = ((double)abc[cc]->h[k] + (double)abc[cc]->l[k]) - D.ref[k];
+        const double bc0 = p[1][1] * p[2][2] - p[1][2] * p[2][1];
+        const double bc1 = p[1][2] * p[2][0] - p[1][0] * p[2][2];
+        const double bc2 = p[1][0] * p[2][1] - p[1][1] * p[2][0];
+        v = (p[0][0] * bc0 + p[0][1] * bc1 + p[0][2] * bc2) / 6.0;
+        double d1[3], d2[3];
+        for (int k = 0; k < 3; ++k) {
+            d1[k] = p[1][k] - p[0][k];
+            d2[k] = p[2][k] - p[0][k];
+        }
+        const double n0 = d1[1] * d2[2] - d1[2] * d2[1];
+        const double n1 = d1[2] * d2[0] - d1[0] * d2[2];
+        const double n2 = d1[0] * d2[1] - d1[1] * d2[0];
+        ar = 0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    }
+    sv[threadIdx.x] = v;
+    sa[threadIdx.x] = ar;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            sv[threadIdx.x] += sv[threadIdx.x + k];
+            sa[threadIdx.x] += sa[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        P.tri_part[blockIdx.x] = sv[0];
+        P.tri_part[P.n_chunks + blockIdx.x] = sa[0];
+    }
+}
+
+// V0 of each droplet = the same fixed-order sum the volume penalty uses.
+__global__ void __launch_bounds__(64) k_set_v0(DevPtrs P) {
+    DropDev *D = P.drops + blockIdx.x;
+    const double V = droplet_partial_sum(P.tri_part, D->chunk_off, D->n_chunks, threadIdx.x);
+    if (threadIdx.x == 0) D->V0 = V;
+}
+
+// -------------------------------------------------------------- node pass
+// One wavefront (workgroup) per block of 64 nodes.  Per node: gather over
+// its incident triangles (CSR, ascending triangle id) the corner
+// surface-tension forces, the 1-ring area chi, the sum of unit face normals
+// and the volume gradient; then the wetting force -chi Pi(d) n/3 with Pi
+// from integer powers (Eq. 10) and the optional volume penalty.  Also: base
+// cell floor(q - 1/2) (decided exactly from the hi/lo pair), the four
+// Peskin weights per axis and the block's stencil bounding box.  Mode 0
+// (a time step) also stamps every tile holding a stencil cell with the
+// epoch and spreads the block's forces (Eq. 8) into an LDS copy of its
+// stencil box, node by node in ascending order (each lane one of the 64
+// stencil points, so no two lanes touch the same cell; node data are read
+// from LDS as broadcasts), then writes that partial region out for the tile
+// gather.
+template <typename R>
+__global__ void __launch_bounds__(64) k_node(DevPtrs P, int mode) {
+    __shared__ R reg[3 * MAXP];
+    __shared__ R nw[12][NB], nf[3][NB];
+    __shared__ int nbs[3][NB];
+    const int lane = threadIdx.x;
+    const int blk = blockIdx.x;
+    const int d = P.blk_drop[blk];
+    const DropDev &D = P.drops[d];
+    const BoxDev &B = P.boxes[D.box];
+    const int N = P.Ntot, T = P.Ttot;
+    const R *qh = (const R *)P.qh, *ql = (const R *)P.ql;
+    const R *tr = (const R *)P.trec;
+    const int j = blk * NB + lane;
+    const bool valid = (j - D.node_off) < D.n_nodes;
+    const bool zper = B.zbc == 1;
+    const int dims[3] = {B.nx, B.ny, B.nz};
+    double dV = 0.0;
+    if (D.kvol > 0.0) {
+        const double V = droplet_partial_sum(P.tri_part, D.chunk_off, D.n_chunks, lane);
+        dV = (V - D.V0) / D.V0;
+    }
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+    R w[12], f[3];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[k] = 0;
+    f[0] = f[1] = f[2] = 0;
+    int b[3] = {0, 0, 0};
+    if (valid) {
+        const Node3<R> qj = load_node(qh, ql, N, j);
+        R st[3] = {0, 0, 0}, ns[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
+        R chi = 0;
+        const int e0 = P.csr_off[j], e1 = P.csr_off[j + 1];
+        for (int e = e0; e < e1; e += 8) {
+            int code[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) code[k] = e + k < e1 ? P.csr_ent[e + k] : -1;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (code[k] < 0) continue;
+                const int t = code[k] / 3, c = code[k] - 3 * t;
+                chi += tr[t];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    ns[a] += tr[(1 + a) * T + t];
+                    gv[a] += tr[(4 + a) * T + t];
+                    st[a] += tr[(7 + 3 * c + a) * T + t];
+                }
+            }
+        }
+        const R nl = R(1) / sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);
+        const R dist = qj.h[2] + qj.l[2];
+        if (!(dist > R(0))) atomicOr(P.status, BIT_WALL);
+        const R rr = (R)D.xi / dist;
+        R pn = 1, pm = 1;
+        for (int k = 0; k < D.n_exp; ++k) pn *= rr;
+        for (int k = 0; k < D.m_exp; ++k) pm *= rr;
+        const R Pi = (R)D.A * (pn - pm);
+        const R kw = chi * Pi / R(3) * nl;
+        const R kv = (R)(-D.kvol * dV);
+        R *phi = (R *)P.phi;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            f[k] = st[k] - kw * ns[k] + kv * gv[k];
+            phi[k * N + j] = f[k];
+        }
+
+        // base cell and Peskin 4-point weights per axis.  With t = q - b - 1/2
+        // in [0,1] all four weights share s = sqrt(1 + 4t(1-t)):
+        //   b-1: (3 - 2t - s)/8, b: (3 - 2t + s)/8, b+1: (1 + 2t + s)/8,
+        //   b+2: (1 + 2t - s)/8.
+        R *wg = (R *)P.wgt;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            R qa = qj.h[a], la = qj.l[a];
+            if (!(fabs(qa) < R(1.0e7))) {  // non-finite or absurd: flag, keep indices sane
+                atomicOr(P.status, BIT_JUMP);
+                qa = R(0.5);
+                la = R(0);
+            }
+            const R fl = floor(qa);
+            const R rf = (qa - fl - R(0.5)) + la;
+            const bool neg = rf < R(0);
+            b[a] = (int)fl - (neg ? 1 : 0);
+            const R t = neg ? rf + R(1) : rf;
+            const R s = sqrt(R(1) + R(4) * t * (R(1) - t));
+            w[4 * a + 0] = (R(3) - R(2) * t - s) * R(0.125);
+            w[4 * a + 1] = (R(3) - R(2) * t + s) * R(0.125);
+            w[4 * a + 2] = (R(1) + R(2) * t + s) * R(0.125);
+            w[4 * a + 3] = (R(1) + R(2) * t - s) * R(0.125);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) wg[(4 * a + o) * N + j] = w[4 * a + o];
+            P.base[a * N + j] = b[a];
+            const bool per = a < 2 || zper;
+            P.s0[a * N + j] = per ? wrapn(b[a] - 1, dims[a]) : b[a] - 1;
+            lo[a] = b[a] - 1;
+            hi[a] = b[a] + 2;
+        }
+        if (mode == 0) {
+            // epoch stamp of every tile holding a stencil cell (same value
+            // from every writer, so plain stores)
+            const int ctr = *P.ctr;
+            int tl[3][4], tn[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                tn[a] = 0;
+                const bool per = a < 2 || zper;
+                for (int o = 0; o < 4; ++o) {
+                    int c = lo[a] + o;
+                    if (per) c = wrapn(c, dims[a]);
+                    else if (c < 0 || c >= dims[a]) continue;
+                    const int tt = c >> 2;
+                    if (tn[a] == 0 || tl[a][tn[a] - 1] != tt) tl[a][tn[a]++] = tt;
+                }
+            }
+            for (int iz = 0; iz < tn[2]; ++iz)
+                for (int iy = 0; iy < tn[1]; ++iy)
+                    for (int ix = 0; ix < tn[0]; ++ix)
+                        ((IBLB_GLOBAL int32_t *)B.stamp)[((int64_t)tl[2][iz] * B.tny + tl[1][iy]) *
+                                                              B.tnx + tl[0][ix]] = ctr;
+        }
+    }
+    // stencil bounding box of the block (unwrapped cell indices)
+    int bl[3], bh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bl[a] = wave_min(lo[a]);
+        bh[a] = wave_max(hi[a]);
+        if (lane == 0) {
+            P.bbox[(2 * a) * P.nblk + blk] = bl[a];
+            P.bbox[(2 * a + 1) * P.nblk + blk] = bh[a];
+        }
+    }
+    if (mode != 0) return;
+    // partial spread over the block's stencil box
+    int zl = bl[2], zh = bh[2];
+    if (!zper) {
+        zl = max(zl, 0);
+        zh = min(zh, B.nz - 1);
+    }
+    const int ex = bh[0] - bl[0] + 1, ey = bh[1] - bl[1] + 1, ez = zh - zl + 1;
+    const bool ovf = ex > B.nx || ey > B.ny || (zper && ez > B.nz) || ez < 1 ||
+                     (int64_t)ex * ey * ez > MAXP;
+    if (lane == 0) {
+        int32_t *br = P.breg + (int64_t)blk * BREG;
+        br[0] = wrapn(bl[0], B.nx);
+        br[1] = wrapn(bl[1], B.ny);
+        br[2] = zper ? wrapn(zl, B.nz) : zl;
+        br[3] = ex;
+        br[4] = ey;
+        br[5] = ez;
+        br[6] = ovf ? 1 : 0;
+        br[7] = 0;
+    }
+    if (ovf) return;
+    const int ncell = ex * ey * ez;
+    for (int c = lane; c < ncell; c += 64) {
+        reg[c] = R(0);
+        reg[MAXP + c] = R(0);
+        reg[2 * MAXP + c] = R(0);
+    }
+    // the block's node data, read back by every lane as broadcasts
+#pragma unroll
+    for (int k = 0; k < 12; ++k) nw[k][lane] = w[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        nf[k][lane] = f[k];
+        nbs[k][lane] = b[k] - 1 - (k == 0 ? bl[0] : (k == 1 ? bl[1] : zl));
+    }
+    __syncthreads();
+    const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
+    const int nvalid = min(NB, D.n_nodes - (blk * NB - D.node_off));
+    for (int nl = 0; nl < nvalid; ++nl) {
+        const int rz = nbs[2][nl] + oz;  // region coordinates of this lane's stencil cell
+        const int ry = nbs[1][nl] + oy;
+        const int rx = nbs[0][nl] + ox;
+        const R wv = nw[ox][nl] * nw[4 + oy][nl] * nw[8 + oz][nl];
+        if (rz >= 0 && rz < ez) {  // outside only for wall layers (dropped)
+            const int c = (rz * ey + ry) * ex + rx;
+            reg[c] += nf[0][nl] * wv;
+            reg[MAXP + c] += nf[1][nl] * wv;
+            reg[2 * MAXP + c] += nf[2][nl] * wv;
+        }
+    }
+    __syncthreads();
+    IBLB_GLOBAL R *out = (IBLB_GLOBAL R *)P.part + (int64_t)blk * 3 * MAXP;
+    for (int c = lane; c < ncell; c += 64) {
+        out[c] = reg[c];
+        out[MAXP + c] = reg[MAXP + c];
+        out[2 * MAXP + c] = reg[2 * MAXP + c];
+    }
+}
+
+// ----------------------------------------------------- stamped-tile list
+// One wavefront per chunk of 64 tiles appends the chunk's stamped tiles to
+// the list of this epoch (one integer atomic per chunk; the order of the
+// list does not affect any result).  Also clears the other epoch's count.
+__global__ void __launch_bounds__(256) k_compact(DevPtrs P) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ctr = *P.ctr;
+    const int slot = ctr & 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.tile_count[slot ^ 1] = 0;
+    if (c >= P.total_tiles / TILE_CELLS) return;
+    const BoxDev &B = P.boxes[P.tchunk_box[c]];
+    const int lt = c * TILE_CELLS + lane - B.tile_base;
+    const bool st = lt < B.n_tiles && ((const IBLB_GLOBAL int32_t *)B.stamp)[lt] == ctr;
+    const uint64_t m = __ballot(st);
+    if (m == 0) return;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(P.tile_count + slot, __popcll(m));
+    base = __shfl(base, 0, 64);
+    if (st) P.tile_list[base + __popcll(m & ((1ull << lane) - 1ull))] = c * TILE_CELLS + lane;
+}
+
+// ---------------------------------------------------- interpolate + advect
+// One workgroup (4 wavefronts) per node block.  The velocity over the
+// block's stencil box is staged in LDS when it fits; wavefront w sums the
+// z-slab w of every node's 4x4x4 stencil (Eq. 7, u = 0 on wall cells), the
+// four slab sums are added in slab order, and wavefront 0 advances q by
+// forward Euler with a compensated (hi, lo) sum.  mode 1 writes U to Uout
+// instead of moving the nodes.  Block 0 advances the step epoch.
+template <typename R>
+__global__ void __launch_bounds__(256) k_interp(DevPtrs P, int mode, double *Uout) {
+    constexpr int MAXR = 36864 / (3 * (int)sizeof(R));
+    __shared__ R su[3 * MAXR];
+    __shared__ R red[3][3][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int blk = blockIdx.x;
+    const DropDev &D = P.drops[P.blk_drop[blk]];
+    const BoxDev &B = P.boxes[D.box];
+    const int N = P.Ntot, nb = P.nblk;
+    const bool zper = B.zbc == 1;
+    const IBLB_GLOBAL R *ub = (const IBLB_GLOBAL R *)B.uband;
+    const int bx0 = P.bbox[0 * nb + blk], bx1 = P.bbox[1 * nb + blk];
+    const int by0 = P.bbox[2 * nb + blk], by1 = P.bbox[3 * nb + blk];
+    int bz0 = P.bbox[4 * nb + blk], bz1 = P.bbox[5 * nb + blk];
+    if (!zper) {
+        bz0 = max(bz0, 0);
+        bz1 = min(bz1, B.nz - 1);
+    }
+    const int ex = bx1 - bx0 + 1, ey = by1 - by0 + 1, ez = bz1 - bz0 + 1;
+    const bool staged = ex > 0 && ey > 0 && ez > 0 && (int64_t)ex * ey * ez <= MAXR;
+    auto gidx = [&](int x, int y, int z) -> int64_t {
+        const int64_t tile = ((int64_t)(z >> 2) * B.tny + (y >> 2)) * B.tnx + (x >> 2);
+        return tile * 3 * TILE_CELLS + (((z & 3) << 4) | ((y & 3) << 2) | (x & 3));
+    };
+    if (staged) {
+        const int x0w = wrapn(bx0, B.nx);
+        for (int r = tid >> 4; r < ey * ez; r += 16) {
+            const int iz = r / ey, iy = r - iz * ey;
+            const int y = wrapn(by0 + iy, B.ny);
+            const int z = zper ? wrapn(bz0 + iz, B.nz) : bz0 + iz;
+            for (int ix = tid & 15; ix < ex; ix += 16) {
+                int x = x0w + ix;
+                while (x >= B.nx) x -= B.nx;
+                const int64_t g = gidx(x, y, z);
+                const int c = r * ex + ix;
+                su[c] = ub[g];
+                su[MAXR + c] = ub[g + TILE_CELLS];
+                su[2 * MAXR + c] = ub[g + 2 * TILE_CELLS];
+            }
+        }
+    }
+    __syncthreads();
+    const int j = blk * NB + lane;
+    const bool valid = j - D.node_off < D.n_nodes;
+    R U0 = 0, U1 = 0, U2 = 0;
+    if (valid) {
+        const R *wg = (const R *)P.wgt;
+        const int bx = P.base[j], by = P.base[N + j], bz = P.base[2 * N + j];
+        const int z = bz - 1 + wave;
+        if (zper || (z >= 0 && z < B.nz)) {
+            const R wz = wg[(8 + wave) * N + j];
+            R wx[4], wy[4];
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                wx[o] = wg[o * N + j];
+                wy[o] = wg[(4 + o) * N + j];
+            }
+            if (staged) {
+#pragma unroll
+                for (int oy = 0; oy < 4; ++oy) {
+                    const int c0 = ((z - bz0) * ey + (by - 1 + oy - by0)) * ex + (bx - 1 - bx0);
+#pragma unroll
+                    for (int ox = 0; ox < 4; ++ox) {
+                        const R w = wx[ox] * wy[oy] * wz;
+                        U0 += su[c0 + ox] * w;
+                        U1 += su[MAXR + c0 + ox] * w;
+                        U2 += su[2 * MAXR + c0 + ox] * w;
+                    }
+                }
+            } else {
+                const int zw = zper ? wrapn(z, B.nz) : z;
+                for (int oy = 0; oy < 4; ++oy) {
+                    const int y = wrapn(by - 1 + oy, B.ny);
+                    for (int ox = 0; ox < 4; ++ox) {
+                        const R w = wx[ox] * wy[oy] * wz;
+                        const int64_t g = gidx(wrapn(bx - 1 + ox, B.nx), y, zw);
+                        U0 += ub[g] * w;
+                        U1 += ub[g + TILE_CELLS] * w;
+                        U2 += ub[g + 2 * TILE_CELLS] * w;
+                    }
+                }
+            }
+        }
+    }
+    if (wave > 0) {
+        red[wave - 1][0][lane] = U0;
+        red[wave - 1][1][lane] = U1;
+        red[wave - 1][2][lane] = U2;
+    }
+    __syncthreads();
+    if (wave == 0 && valid) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            U0 += red[k][0][lane];
+            U1 += red[k][1][lane];
+            U2 += red[k][2][lane];
+        }
+        if (mode == 1) {
+            Uout[3 * j + 0] = U0;
+            Uout[3 * j + 1] = U1;
+            Uout[3 * j + 2] = U2;
+        } else {
+            R *qh = (R *)P.qh, *ql = (R *)P.ql;
+            const R U[3] = {U0, U1, U2};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const R h = qh[a * N + j], l = ql[a * N + j];
+                // two-sum h + U, fold the error into the low part, renormalise
+                const R s = h + U[a];
+                const R bb = s - h;
+                const R err = (h - (s - bb)) + (U[a] - bb);
+                const R l2 = l + err;
+                const R h2 = s + l2;
+                qh[a * N + j] = h2;
+                ql[a * N + j] = l2 - (h2 - s);
+            }
+            if (fabs(U0) > R(1) || fabs(U1) > R(1) || fabs(U2) > R(1)) atomicOr(P.status, BIT_JUMP);
+        }
+    }
+    if (mode == 0 && blk == 0 && tid == 0) *P.ctr = *P.ctr + 1;
+}
+
+__global__ void k_epoch(DevPtrs P) {
+    if (threadIdx.x == 0) *P.ctr = *P.ctr + 1;
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------ observables
+__device__ __forceinline__ double block_sum256(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ double block_minmax256(double v, double *sh, bool mx) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + s])
+                                 : fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Per droplet (one workgroup): z range, FP64 area, volume and area-weighted
+// centroid, then the edge crossings of z = z_min + xi.
+template <typename R>
+__global__ void __launch_bounds__(256) k_drop_obs(DevPtrs P) {
+    __shared__ double sh[256];
+    const DropDev &D = P.drops[blockIdx.x];
+    const R *qh = (const R *)P.qh, *ql = (const R *)P.ql;
+    const int N = P.Ntot;
+    auto pos = [&](int j, int a) { return (double)qh[a * N + j] + (double)ql[a * N + j]; };
+    double zmin = DBL_MAX, zmax = -DBL_MAX;
+    for (int k = threadIdx.x; k < D.n_nodes; k += 256) {
+        const double z = pos(D.node_off + k, 2);
+        zmin = fmin(zmin, z);
+        zmax = fmax(zmax, z);
+    }
+    zmin = block_minmax256(zmin, sh, false);
+    zmax = block_minmax256(zmax, sh, true);
+    double vol = 0, area = 0, c0 = 0, c1 = 0, c2 = 0;
+    for (int t = D.tri_off + threadIdx.x; t < D.tri_off + D.n_tris; t += 256) {
+        double p[3][3];
+        for (int c = 0; c < 3; ++c)
+            for (int a = 0; a < 3; ++a) p[c][a] = pos(P.tri[3 * t + c], a) - D.ref[a];
+        const double bc0 = p[1][1] * p[2][2] - p[1][2] * p[2][1];
+        const double bc1 = p[1][2] * p[2][0] - p[1][0] * p[2][2];
+        const double bc2 = p[1][0] * p[2][1] - p[1][1] * p[2][0];
+        vol += (p[0][0] * bc0 + p[0][1] * bc1 + p[0][2] * bc2) / 6.0;
+        double e1[3], e2[3];
+        for (int a = 0; a < 3; ++a) {
+            e1[a] = p[1][a] - p[0][a];
+            e2[a] = p[2][a] - p[0][a];
+        }
+        const double n0 = e1[1] * e2[2] - e1[2] * e2[1];
+        const double n1 = e1[2] * e2[0] - e1[0] * e2[2];
+        const double n2 = e1[0] * e2[1] - e1[1] * e2[0];
+        const double At = 0.5 * sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        area += At;
+        c0 += At * (p[0][0] + p[1][0] + p[2][0]) / 3.0;
+        c1 += At * (p[0][1] + p[1][1] + p[2][1]) / 3.0;
+        c2 += At * (p[0][2] + p[1][2] + p[2][2]) / 3.0;
+    }
+    vol = block_sum256(vol, sh);
+    area = block_sum256(area, sh);
+    c0 = block_sum256(c0, sh) / area + D.ref[0];
+    c1 = block_sum256(c1, sh) / area + D.ref[1];
+    c2 = block_sum256(c2, sh) / area + D.ref[2];
+    const double zc = zmin + D.xi;
+    double rs = 0, cnt = 0;
+    for (int t = D.tri_off + threadIdx.x; t < D.tri_off + D.n_tris; t += 256) {
+        for (int c = 0; c < 3; ++c) {
+            const int a = P.tri[3 * t + c], b = P.tri[3 * t + (c + 1) % 3];
+            if (a > b) continue;
+            const double za = pos(a, 2), zb = pos(b, 2);
+            if ((za < zc) == (zb < zc)) continue;
+            const double s = (zc - za) / (zb - za);
+            const double px = pos(a, 0) + s * (pos(b, 0) - pos(a, 0)) - c0;
+            const double py = pos(a, 1) + s * (pos(b, 1) - pos(a, 1)) - c1;
+            rs += sqrt(px * px + py * py);
+            cnt += 1.0;
+        }
+    }
+    rs = block_sum256(rs, sh);
+    cnt = block_sum256(cnt, sh);
+    if (threadIdx.x == 0) {
+        double *o = P.obs_out + blockIdx.x * OBS_DROP;
+        o[0] = vol;
+        o[1] = area;
+        o[2] = zmin;
+        o[3] = zmax;
+        o[4] = c0;
+        o[5] = c1;
+        o[6] = c2;
+        o[7] = rs;
+        o[8] = cnt;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_tri(const DevPtrs &P, bool f64, hipStream_t s) {
+    if (P.n_chunks == 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(k_tri<double>, dim3(P.n_chunks), dim3(256), 0, s, P);
+    else hipLaunchKernelGGL(k_tri<float>, dim3(P.n_chunks), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_v0(const DevPtrs &P, bool, hipStream_t s) {
+    if (P.n_drops == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_v0, dim3(P.n_drops), dim3(64), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_node(const DevPtrs &P, bool f64, int mode, hipStream_t s) {
+    if (P.nblk == 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(k_node<double>, dim3(P.nblk), dim3(64), 0, s, P, mode);
+    else hipLaunchKernelGGL(k_node<float>, dim3(P.nblk), dim3(64), 0, s, P, mode);
+    if (mode == 0 && P.total_tiles > 0) {
+        const int chunks = P.total_tiles / TILE_CELLS;
+        hipLaunchKernelGGL(k_compact, dim3((chunks + 3) / 4), dim3(256), 0, s, P);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_interp(const DevPtrs &P, bool f64, int mode, double *Uout, hipStream_t s) {
+    if (P.nblk == 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(k_interp<double>, dim3(P.nblk), dim3(256), 0, s, P, mode, Uout);
+    else hipLaunchKernelGGL(k_interp<float>, dim3(P.nblk), dim3(256), 0, s, P, mode, Uout);
+    return hipGetLastError();
+}
+
+hipError_t launch_epoch(const DevPtrs &P, hipStream_t s) {
+    hipLaunchKernelGGL(k_epoch, dim3(1), dim3(64), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t g = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_drop_obs(const DevPtrs &P, bool f64, hipStream_t s) {
+    if (P.n_drops == 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(k_drop_obs<double>, dim3(P.n_drops), dim3(256), 0, s, P);
+    else hipLaunchKernelGGL(k_drop_obs<float>, dim3(P.n_drops), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+
+}  // namespace iblb
