@@ -68,6 +68,9 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP/HSA runtime; loading it first makes this
+    # library bind to the same runtime instead of a second copy from /opt/rocm
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2604_17463_amd/build.py "
                            "(or __graft_entry__.build()); there is no fallback path")

@@ -594,12 +594,19 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     }
     c->ws = (char *)dev_workspace;
     c->stream = (hipStream_t)hip_stream;
-    if (hipStreamCreateWithFlags(&c->ib, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-        const std::string m = "stream/event creation failed";
-        iblb_destroy(c);
-        return set_err(nullptr, IBLB_E_DEVICE, m);
+    {
+        hipError_t e = hipStreamCreateWithFlags(&c->ib, hipStreamNonBlocking);
+        const char *what = "hipStreamCreateWithFlags";
+        if (e == hipSuccess) {
+            e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+            what = "hipEventCreateWithFlags";
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            const std::string m = std::string(what) + ": " + hipGetErrorString(e);
+            iblb_destroy(c);
+            return set_err(nullptr, IBLB_E_DEVICE, m);
+        }
     }
     auto at = [&](size_t off) { return (void *)(c->ws + off); };
     DevPtrs &P = c->P;

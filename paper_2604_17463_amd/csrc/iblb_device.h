@@ -77,6 +77,10 @@ template <> __device__ __forceinline__ double bcast<double>(double v, int l) {
 }
 __device__ __forceinline__ int bcast_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+template <typename R> struct Vec4;
+template <> struct Vec4<float> { using T = float4; };
+template <> struct Vec4<double> { using T = double4; };
+
 template <typename R> __device__ __forceinline__ R pick4(int o, R a0, R a1, R a2, R a3) {
     return o == 0 ? a0 : (o == 1 ? a1 : (o == 2 ? a2 : (o == 3 ? a3 : R(0))));
 }

@@ -22,10 +22,12 @@ constexpr int TILE = 4;
 constexpr int TILE_CELLS = 64;
 constexpr int NB = 64;           // nodes per block
 constexpr int TRI_CHUNK = 256;   // triangles per FP64 partial-sum chunk
-constexpr int TREC = 16;
+constexpr int TREC = 20;         // per-triangle record: five four-vectors (A, n), (N/6, 0),
+                                 // and the corner forces (f_c, 0) of corners c = 0, 1, 2
+static_assert(TREC == 5 * 4, "triangle record = five four-vectors");
 constexpr int K1_MAX_THREADS = 256; // launch bound of the bulk stream-collide kernel
 constexpr int MAXP = 2048;          // cells of a node block's partial-spread region
-constexpr int BREG = 8;             // ints per block region descriptor         // per-triangle record: A, n(3), N/6(3), 3 corner forces(9)
+constexpr int BREG = 8;             // ints per block region descriptor
 
 // Velocity set in the library's order: 0 = rest, i and i+9 opposite (i=1..9).
 __host__ __device__ constexpr int cx_of(int i) {
@@ -90,7 +92,7 @@ struct DevPtrs {
     // node arrays, SoA [3][Ntot] unless stated
     void *qh, *ql;              // position, high and low parts (Real)
     void *phi;                  // nodal force (Real)
-    void *trec;                 // [TREC][Ttot] per-triangle records (Real)
+    void *trec;                 // [Ttot][TREC] per-triangle records (Real)
     int32_t *tile_list;         // stamped tiles of the current epoch (global ids)
     int32_t *tile_count;        // [2] list lengths, indexed by epoch parity
     void *wgt;                  // [12][Ntot] Peskin weights x0..3,y0..3,z0..3 (Real)

@@ -10,7 +10,7 @@ namespace iblb {
 // One thread per triangle (a,b,c): N = (q_b - q_a) x (q_c - q_a), area
 // A_t = |N|/2, unit normal n_t, the volume-gradient share N/6 and the three
 // corner forces -sigma dA_t/dq = (sigma/2)(q_prev - q_next) x n_t, stored as
-// a record [TREC][Ttot] for the node gather.  Also the FP64 volume
+// a record of five four-vectors per triangle for the node gather.  Also the FP64 volume
 // sum_t (a-r).((b-r)x(c-r))/6 and area per chunk of 256 triangles
 // (positions relative to the droplet's reference point r), fixed tree.
 
@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(256) k_tri(DevPtrs P) {
     const DropDev &D = P.drops[ch.drop];
     const R *qh = (const R *)P.qh, *ql = (const R *)P.ql;
     const int t = ch.t0 + threadIdx.x;
-    const int T = P.Ttot, N = P.Ntot;
+    const int N = P.Ntot;
     double v = 0.0, ar = 0.0;
     if (t < ch.t1) {
         const Node3<R> a = load_node(qh, ql, N, P.tri[3 * t]);
@@ -41,16 +41,13 @@ __global__ void __launch_bounds__(256) k_tri(DevPtrs P) {
         cross3(cb, nt, f0);
         cross3(ac, nt, f1);
         cross3(ba, nt, f2);
-        R *tr = (R *)P.trec;
-        tr[0 * T + t] = R(0.5) * len;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            tr[(1 + k) * T + t] = nt[k];
-            tr[(4 + k) * T + t] = Nt[k] / R(6);
-            tr[(7 + k) * T + t] = hs * f0[k];
-            tr[(10 + k) * T + t] = hs * f1[k];
-            tr[(13 + k) * T + t] = hs * f2[k];
-        }
+        using V4 = typename Vec4<R>::T;
+        V4 *tr = (V4 *)P.trec + (int64_t)t * (TREC / 4);
+        tr[0] = V4{R(0.5) * len, nt[0], nt[1], nt[2]};
+        tr[1] = V4{Nt[0] / R(6), Nt[1] / R(6), Nt[2] / R(6), R(0)};
+        tr[2] = V4{hs * f0[0], hs * f0[1], hs * f0[2], R(0)};
+        tr[3] = V4{hs * f1[0], hs * f1[1], hs * f1[2], R(0)};
+        tr[4] = V4{hs * f2[0], hs * f2[1], hs * f2[2], R(0)};
         double p[3][3];
         const Node3<R> *abc[3] = {&a, &b, &c};
 #pragma unroll
@@ -119,9 +116,10 @@ __global__ void __launch_bounds__(64) k_node(DevPtrs P, int mode) {
     const int d = P.blk_drop[blk];
     const DropDev &D = P.drops[d];
     const BoxDev &B = P.boxes[D.box];
-    const int N = P.Ntot, T = P.Ttot;
+    const int N = P.Ntot;
     const R *qh = (const R *)P.qh, *ql = (const R *)P.ql;
-    const R *tr = (const R *)P.trec;
+    using V4 = typename Vec4<R>::T;
+    const V4 *tr = (const V4 *)P.trec;
     const int j = blk * NB + lane;
     const bool valid = (j - D.node_off) < D.n_nodes;
     const bool zper = B.zbc == 1;
@@ -150,13 +148,19 @@ __global__ void __launch_bounds__(64) k_node(DevPtrs P, int mode) {
             for (int k = 0; k < 8; ++k) {
                 if (code[k] < 0) continue;
                 const int t = code[k] / 3, c = code[k] - 3 * t;
-                chi += tr[t];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    ns[a] += tr[(1 + a) * T + t];
-                    gv[a] += tr[(4 + a) * T + t];
-                    st[a] += tr[(7 + 3 * c + a) * T + t];
-                }
+                const V4 r0 = tr[(int64_t)t * (TREC / 4)];
+                const V4 r1 = tr[(int64_t)t * (TREC / 4) + 1];
+                const V4 rf = tr[(int64_t)t * (TREC / 4) + 2 + c];
+                chi += r0.x;
+                ns[0] += r0.y;
+                ns[1] += r0.z;
+                ns[2] += r0.w;
+                gv[0] += r1.x;
+                gv[1] += r1.y;
+                gv[2] += r1.z;
+                st[0] += rf.x;
+                st[1] += rf.y;
+                st[2] += rf.z;
             }
         }
         const R nl = R(1) / sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);

@@ -1,0 +1,48 @@
+"""Driver for rocprofv3 runs of the bulk stream-collide kernel.
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT -- python -m paper_2604_17463_amd.profiling
+    rocprofv3 --pmc WRITE_SIZE -d OUT -- python -m paper_2604_17463_amd.profiling
+    rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2604_17463_amd.profiling
+
+First a plain device copy of a known size (torch's copy kernel) serves as
+the calibration of the memory counters, then the bulk kernel runs `reps`
+times on the 128x128x64 spreading workload and on a 256x256x128 box.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--storage", type=int, default=1)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    args = ap.parse_args()
+    import torch
+
+    import paper_2604_17463_amd as P
+    from iblb_inputs import configs
+    from iblb_inputs.configs import Box, Workload
+
+    n = args.copy_mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    res = {"copy_bytes_each_way": n * 4}
+    for name, wl in (("spreading", configs.spreading_c2()),
+                     ("box256", Workload("box-256x256x128", [Box(256, 256, 128, tau=0.6)], []))):
+        sim = P.Simulation(wl, storage=args.storage, flags=P.IBLB_FLAG_AUTOTUNE,
+                           dev_scale=4096.0 if args.storage == 2 else 1.0)
+        ms = sim.time_stream_collide(reps=args.reps)
+        res[name] = {"workload": wl.name, "cells": wl.cells, "bulk_ms": ms,
+                     "launch": list(sim.get_launch())}
+        sim.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -332,3 +332,43 @@ def test_set_launch_rejects_shapes_beyond_the_kernel_bound():
     s.set_launch(64, 4)
     assert s.get_launch() == (64, 4)
     s.step(3)
+
+
+# ---------------------------------------------------------------- full size
+# The 128x128x64 spreading workload (10,242 nodes) in the launch configuration
+# the benchmark times (graph replay, autotuned bulk launch shape).
+
+def test_spreading_forces_match_oracle_at_full_size():
+    say("spreading forces full size")
+    wl = configs.spreading_c2()
+    d = wl.droplets[0]
+    s = sim(wl, F32, flags=GRAPH | AUTOTUNE)
+    s.step(50)
+    qg = s.read_nodes(0)
+    A = oracle.wetting_A(d.sigma, d.theta_eq, d.xi, d.n_exp, d.m_exp)
+    want = oracle.node_forces(d.tris, qg, d.sigma, A, d.xi, d.n_exp, d.m_exp, d.k_vol,
+                              oracle.volume(d.tris, d.nodes))["phi"]
+    got = s.compute_forces(0)
+    assert np.abs(got - want).max() < 2e-5 * np.abs(want).max()
+
+
+def test_spreading_step_matches_oracle_from_gpu_state(perm):
+    # sampled parity at full size: the oracle advances the GPU's own state
+    # (populations and nodes after 200 steps) by one step; the GPU's next
+    # step must agree to FP32 rounding
+    say("spreading one-step parity full size")
+    wl = configs.spreading_c2()
+    s = sim(wl, F32, flags=GRAPH | AUTOTUNE)
+    s.step(200)
+    f0 = to_oracle(s.read_state(0), perm)
+    q0 = s.read_nodes(0)
+    ref = oracle.OracleSim(wl, f0=[f0])
+    ref.q[0] = q0.copy()
+    ref.step(1)
+    s.step(1)
+    f1 = to_oracle(s.read_state(0), perm)
+    assert rel_l2(deviation(f1), deviation(ref.f[0])) < 1e-5
+    assert np.abs(s.read_nodes(0) - ref.q[0]).max() < 1e-6
+    drops, boxes = s.observables()
+    assert boxes[0]["status_bits"] == 0
+    assert abs(boxes[0]["mass"] - oracle.mass(ref.f[0])) < 1e-9 * oracle.mass(ref.f[0])
