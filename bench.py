@@ -208,7 +208,8 @@ def main():
     sim.close()
     tr = traffic_record()
     traffic = None
-    if tr and tr.get("workload") == wl.name and tr.get("storage") == args.storage:
+    if (tr and tr.get("workload") == wl.name and tr.get("storage") == args.storage
+            and tuple(tr.get("launch", ())) == tuple(launch)):
         traffic = tr["hbm_bytes_per_launch"]
     out = {
         "metric": METRIC, "value": round(mlups, 3), "unit": "MLUPS", "n_gpus": 1,

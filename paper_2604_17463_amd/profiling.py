@@ -5,8 +5,9 @@
     rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2604_17463_amd.profiling
 
 First a plain device copy of a known size (torch's copy kernel) serves as
-the calibration of the memory counters, then the bulk kernel runs `reps`
-times on the 128x128x64 spreading workload and on a 256x256x128 box.
+the calibration of the memory counters, then the bulk kernel runs 3 + `reps`
+times in a fixed launch shape on the 128x128x64 spreading workload and on a
+256x256x128 box.
 """
 from __future__ import annotations
 
@@ -19,6 +20,10 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--storage", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--launch-spreading", type=int, nargs=2, default=(128, 1),
+                    help="threads_x rows of the bulk launch on the spreading workload")
+    ap.add_argument("--launch-box", type=int, nargs=2, default=(256, 1),
+                    help="threads_x rows of the bulk launch on the 256x256x128 box")
     args = ap.parse_args()
     import torch
 
@@ -33,10 +38,12 @@ def main():
         b.copy_(a)
     torch.cuda.synchronize()
     res = {"copy_bytes_each_way": n * 4}
-    for name, wl in (("spreading", configs.spreading_c2()),
-                     ("box256", Workload("box-256x256x128", [Box(256, 256, 128, tau=0.6)], []))):
-        sim = P.Simulation(wl, storage=args.storage, flags=P.IBLB_FLAG_AUTOTUNE,
-                           dev_scale=4096.0 if args.storage == 2 else 1.0)
+    for name, wl, launch in (("spreading", configs.spreading_c2(), args.launch_spreading),
+                             ("box256", Workload("box-256x256x128", [Box(256, 256, 128, tau=0.6)], []),
+                              args.launch_box)):
+        sim = P.Simulation(wl, storage=args.storage, dev_scale=4096.0 if args.storage == 2 else 1.0)
+        sim.set_launch(*launch)
+        sim.time_stream_collide(reps=3)
         ms = sim.time_stream_collide(reps=args.reps)
         res[name] = {"workload": wl.name, "cells": wl.cells, "bulk_ms": ms,
                      "launch": list(sim.get_launch())}
