@@ -74,7 +74,10 @@ enum {
 };
 
 typedef struct {
-    int32_t nx, ny, nz; /* cells; nx, ny, nz >= 4 when the box holds a droplet */
+    int32_t nx, ny, nz; /* cells; nx, ny, nz >= 4 when the box holds a droplet;
+                           ten planes of populations (x-rows padded to 128
+                           bytes) may take at most 4 GiB, e.g. about 107 M
+                           cells in FP32, 53 M in FP64 */
     int32_t zbc;        /* IBLB_Z_WALLS or IBLB_Z_PERIODIC                    */
     double tau;         /* BGK relaxation time, > 1/2 (Sec. 2, viscosity
                            mu = rho c_s^2 (tau - 1/2))                         */
@@ -191,11 +194,14 @@ iblb_status iblb_read_csr(struct iblb_ctx *ctx, int32_t d, int32_t *offsets, int
 
 /* Launch shape of the fused stream-collide kernel: threads along x per row
  * (a multiple of 32) and rows handled by one workgroup; their product must be
- * a multiple of 64 and at most 256.  Other shapes return IBLB_E_INVAL.
- * Rebuilds the step graphs.  Synchronising. */
-iblb_status iblb_set_launch(struct iblb_ctx *ctx, int32_t threads_x, int32_t rows_per_group);
+ * a multiple of 64 and at most 256.  streaming_stores (0 or 1) writes the
+ * populations with non-temporal stores, which helps once the two population
+ * buffers exceed the GPU's last-level cache and hurts while they fit.  Other
+ * values return IBLB_E_INVAL.  Rebuilds the step graphs.  Synchronising. */
+iblb_status iblb_set_launch(struct iblb_ctx *ctx, int32_t threads_x, int32_t rows_per_group,
+                            int32_t streaming_stores);
 iblb_status iblb_get_launch(const struct iblb_ctx *ctx, int32_t *threads_x,
-                            int32_t *rows_per_group);
+                            int32_t *rows_per_group, int32_t *streaming_stores);
 
 /* Average device time (ms) of one stream-collide launch over `reps` launches,
  * measured with HIP events on the context's stream (the populations are

@@ -91,8 +91,8 @@ def load():
     L.iblb_interpolate.argtypes = [vp, i32, dp, dp]
     L.iblb_read_bins.argtypes = [vp, i32, ip]
     L.iblb_read_csr.argtypes = [vp, i32, ip, ip]
-    L.iblb_set_launch.argtypes = [vp, i32, i32]
-    L.iblb_get_launch.argtypes = [vp, ip, ip]
+    L.iblb_set_launch.argtypes = [vp, i32, i32, i32]
+    L.iblb_get_launch.argtypes = [vp, ip, ip, ip]
     L.iblb_time_stream_collide.argtypes = [vp, i32, dp]
     L.iblb_destroy.argtypes = [vp]
     L.iblb_last_error.argtypes = [vp]
@@ -269,13 +269,14 @@ class Simulation:
         self._chk(load().iblb_read_csr(self.ctx, d, _iptr(off), _iptr(ent)))
         return off, ent
 
-    def set_launch(self, threads_x, rows):
-        self._chk(load().iblb_set_launch(self.ctx, int(threads_x), int(rows)))
+    def set_launch(self, threads_x, rows, streaming_stores=0):
+        self._chk(load().iblb_set_launch(self.ctx, int(threads_x), int(rows), int(streaming_stores)))
 
     def get_launch(self):
-        a, b = C.c_int32(), C.c_int32()
-        self._chk(load().iblb_get_launch(self.ctx, C.byref(a), C.byref(b)))
-        return a.value, b.value
+        """(threads_x, rows_per_group, streaming_stores) of the bulk kernel."""
+        a, b, n = C.c_int32(), C.c_int32(), C.c_int32()
+        self._chk(load().iblb_get_launch(self.ctx, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
 
     def time_stream_collide(self, reps=10):
         ms = C.c_double()

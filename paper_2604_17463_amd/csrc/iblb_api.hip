@@ -177,8 +177,12 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
         H.b = B;
         H.sx = (int)round_up((size_t)B.nx, 128 / eb);
         H.plane = (int64_t)round_up((size_t)H.sx * B.ny * B.nz, 64);
-        if ((int64_t)B.ny * B.nz >= (1LL << 31) || H.plane * eb >= (1LL << 40))
-            return fail(err, IBLB_E_INVAL, nm + ": box too large");
+        // the stream-collide addresses ten population planes from one base
+        // with 32-bit offsets
+        if ((int64_t)B.ny * B.nz >= (1LL << 31) || 10 * H.plane * eb > (int64_t)BUF_MAX_PLANE_GROUP)
+            return fail(err, IBLB_E_INVAL,
+                        nm + ": box too large (ten population planes must fit in 4 GiB: at most " +
+                            std::to_string(BUF_MAX_PLANE_GROUP / 10 / eb) + " cells incl. x padding)");
         H.tnx = (B.nx + 3) / 4;
         H.tny = (B.ny + 3) / 4;
         H.tnz = (B.nz + 3) / 4;
@@ -478,7 +482,8 @@ iblb_status autotune(iblb_ctx *c) {
     for (auto &H : c->plan.boxes) nxmax = std::max(nxmax, H.b.nx);
     const int saved_parity = c->parity;
     double best = 1e300;
-    int bbx = c->L.bx, bby = c->L.by;
+    int bbx = c->L.bx, bby = c->L.by, bnt = c->L.nt;
+    for (int nt : {0, 1})
     for (int bx : {32, 64, 128, 256}) {
         if (bx > (int)round_up((size_t)nxmax, 32)) continue;
         for (int threads : {64, 128, K1_MAX_THREADS}) {
@@ -486,6 +491,7 @@ iblb_status autotune(iblb_ctx *c) {
             if (by < 1 || check_launch(c, bx, by) != IBLB_OK) continue;
             c->L.bx = bx;
             c->L.by = by;
+            c->L.nt = nt;
             c->rows_per_group = by;
             iblb_status st = upload_rows(c);
             if (st != IBLB_OK) return st;
@@ -500,11 +506,13 @@ iblb_status autotune(iblb_ctx *c) {
                 best = ms;
                 bbx = bx;
                 bby = by;
+                bnt = nt;
             }
         }
     }
     c->L.bx = bbx;
     c->L.by = bby;
+    c->L.nt = bnt;
     c->rows_per_group = bby;
     iblb_status st = upload_rows(c);
     if (st != IBLB_OK) return st;
@@ -777,6 +785,11 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     for (auto &H : p.boxes) nxmax = std::max(nxmax, H.b.nx);
     c->L.bx = nxmax <= 32 ? 32 : (nxmax <= 64 ? 64 : (nxmax <= 128 ? 128 : 256));
     c->L.by = std::max(1, 256 / c->L.bx);
+    // streaming stores once both population buffers exceed the 256 MiB
+    // last-level cache
+    size_t pop_bytes = 0;
+    for (auto &H : p.boxes) pop_bytes += 2 * (size_t)Q * H.plane * elem_bytes(p.storage);
+    c->L.nt = pop_bytes > ((size_t)256 << 20) ? 1 : 0;
     c->rows_per_group = c->L.by;
     st = upload_rows(c);
     if (st == IBLB_OK && (p.flags & IBLB_FLAG_AUTOTUNE)) st = autotune(c);
@@ -1186,23 +1199,26 @@ iblb_status iblb_read_csr(iblb_ctx *c, int32_t d, int32_t *offsets, int32_t *ent
     return IBLB_OK;
 }
 
-iblb_status iblb_set_launch(iblb_ctx *c, int32_t bx, int32_t by) {
+iblb_status iblb_set_launch(iblb_ctx *c, int32_t bx, int32_t by, int32_t nt) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     iblb_status st = check_launch(c, bx, by);
     if (st != IBLB_OK) return st;
+    if (nt != 0 && nt != 1) return set_err(c, IBLB_E_INVAL, "streaming_stores must be 0 or 1");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->L.bx = bx;
     c->L.by = by;
+    c->L.nt = nt;
     c->rows_per_group = by;
     st = upload_rows(c);
     if (st == IBLB_OK) st = build_graphs(c);
     return st;
 }
 
-iblb_status iblb_get_launch(const iblb_ctx *c, int32_t *bx, int32_t *by) {
-    if (!c || !bx || !by) return set_err(nullptr, IBLB_E_INVAL, "NULL argument");
+iblb_status iblb_get_launch(const iblb_ctx *c, int32_t *bx, int32_t *by, int32_t *nt) {
+    if (!c || !bx || !by || !nt) return set_err(nullptr, IBLB_E_INVAL, "NULL argument");
     *bx = c->L.bx;
     *by = c->L.by;
+    *nt = c->L.nt;
     return IBLB_OK;
 }
 

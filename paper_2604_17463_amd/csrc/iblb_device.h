@@ -2,8 +2,6 @@
 #pragma once
 #include "iblb_internal.h"
 
-#include <hip/hip_bf16.h>
-#include <hip/hip_fp16.h>
 
 #include <cfloat>
 #include <climits>
@@ -17,30 +15,42 @@ namespace iblb {
 #define IBLB_GLOBAL __attribute__((address_space(1)))
 
 // ---------------------------------------------------------------- storage
+// Population storage: T in memory, R in registers.  raw() returns the stored
+// value (for FP16 still multiplied by the deviation scale s), put() rounds to
+// nearest even, put_nt() is the same store marked as streaming (no reuse
+// expected before it leaves the caches).
 template <int ST> struct Stor;
 template <> struct Stor<0> {  // FP64 deviations
     using T = double;
     using R = double;
-    static __device__ __forceinline__ R ld(const T *p, float) { return *p; }
-    static __device__ __forceinline__ void st(T *p, R v, float) { *p = v; }
+    static constexpr bool SCALED = false;
+    static __device__ __forceinline__ R raw(const IBLB_GLOBAL T *p) { return *p; }
+    static __device__ __forceinline__ void put(IBLB_GLOBAL T *p, R v) { *p = v; }
+    static __device__ __forceinline__ void put_nt(IBLB_GLOBAL T *p, R v) { __builtin_nontemporal_store(v, p); }
 };
 template <> struct Stor<1> {  // FP32 deviations
     using T = float;
     using R = float;
-    static __device__ __forceinline__ R ld(const T *p, float) { return *p; }
-    static __device__ __forceinline__ void st(T *p, R v, float) { *p = v; }
+    static constexpr bool SCALED = false;
+    static __device__ __forceinline__ R raw(const IBLB_GLOBAL T *p) { return *p; }
+    static __device__ __forceinline__ void put(IBLB_GLOBAL T *p, R v) { *p = v; }
+    static __device__ __forceinline__ void put_nt(IBLB_GLOBAL T *p, R v) { __builtin_nontemporal_store(v, p); }
 };
-template <> struct Stor<2> {  // binary16, scaled deviations
-    using T = __half;
+template <> struct Stor<2> {  // binary16, deviations times s
+    using T = _Float16;
     using R = float;
-    static __device__ __forceinline__ R ld(const T *p, float inv) { return __half2float(*p) * inv; }
-    static __device__ __forceinline__ void st(T *p, R v, float s) { *p = __float2half_rn(v * s); }
+    static constexpr bool SCALED = true;
+    static __device__ __forceinline__ R raw(const IBLB_GLOBAL T *p) { return (R)*p; }
+    static __device__ __forceinline__ void put(IBLB_GLOBAL T *p, R v) { *p = (T)v; }
+    static __device__ __forceinline__ void put_nt(IBLB_GLOBAL T *p, R v) { __builtin_nontemporal_store((T)v, p); }
 };
 template <> struct Stor<3> {  // bfloat16 deviations
-    using T = __hip_bfloat16;
+    using T = __bf16;
     using R = float;
-    static __device__ __forceinline__ R ld(const T *p, float) { return __bfloat162float(*p); }
-    static __device__ __forceinline__ void st(T *p, R v, float) { *p = __float2bfloat16(v); }
+    static constexpr bool SCALED = false;
+    static __device__ __forceinline__ R raw(const IBLB_GLOBAL T *p) { return (R)*p; }
+    static __device__ __forceinline__ void put(IBLB_GLOBAL T *p, R v) { *p = (T)v; }
+    static __device__ __forceinline__ void put_nt(IBLB_GLOBAL T *p, R v) { __builtin_nontemporal_store((T)v, p); }
 };
 
 __device__ __forceinline__ int wrapn(int i, int n) {
@@ -161,59 +171,97 @@ __device__ __forceinline__ RowAddr row_addr(int y, int z, int ny, int nz, int sx
     return a;
 }
 
-// Pre-collision deviations of cell x of the row: the value stored at x - c_i,
-// or, where x - c_i lies in a wall, the opposite population stored at x
-// itself (halfway bounce-back).
+// Byte offsets of cell x and of its periodic x-neighbours x - 1, x + 1
+// within a row.
+struct XOff {
+    uint32_t c, m, p;
+};
+template <uint32_t EB> __device__ __forceinline__ XOff x_off(int x, int nx) {
+    return {(uint32_t)x * EB, (uint32_t)(x == 0 ? nx - 1 : x - 1) * EB,
+            (uint32_t)(x == nx - 1 ? 0 : x + 1) * EB};
+}
+
+// Stored pre-collision deviations of cell x of the row: the value stored at
+// x - c_i, or, where x - c_i lies in a wall, the opposite population stored
+// at x itself (halfway bounce-back).  The row part of every address (plane,
+// source row) depends on `ra` only; when `ra` is the same in all lanes it
+// stays in scalar registers and each load adds only the lane's x offset.
 template <int ST>
-__device__ __forceinline__ void pull(const IBLB_GLOBAL char *__restrict__ src, uint64_t pb,
-                                     const RowAddr &ra, int x, int nx, float inv,
-                                     typename Stor<ST>::R (&g)[Q]) {
+__device__ __forceinline__ void pull_raw(const IBLB_GLOBAL char *__restrict__ src, uint64_t pb,
+                                         const RowAddr &ra, const XOff &xo, typename Stor<ST>::R (&g)[Q]) {
     using S = Stor<ST>;
     using T = typename S::T;
-    constexpr uint32_t EB = sizeof(T);
-    const uint32_t xo = (uint32_t)x * EB;
-    const uint32_t xmo = (uint32_t)(x == 0 ? nx - 1 : x - 1) * EB;
-    const uint32_t xpo = (uint32_t)(x == nx - 1 ? 0 : x + 1) * EB;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
         const bool bb = (cz == 1 && ra.wlo) || (cz == -1 && ra.whi);
-        uint32_t off;
-        const IBLB_GLOBAL char *base;
-        if (bb) {
-            base = src + (uint64_t)opp_of(i) * pb;
-            off = ra.ro[1][1] + xo;
-        } else {
-            base = src + (uint64_t)i * pb;
-            off = ra.ro[cy + 1][cz + 1] + (cx == 1 ? xmo : (cx == -1 ? xpo : xo));
-        }
-        g[i] = S::ld((const T *)(const IBLB_GLOBAL T *)(base + off), inv);
+        const IBLB_GLOBAL char *row = bb ? src + (uint64_t)opp_of(i) * pb + ra.ro[1][1]
+                                         : src + (uint64_t)i * pb + ra.ro[cy + 1][cz + 1];
+        const uint32_t lo = bb ? xo.c : (cx == 1 ? xo.m : (cx == -1 ? xo.p : xo.c));
+        g[i] = S::raw((const IBLB_GLOBAL T *)(row + lo));
+    }
+}
+
+// The same in true (unscaled) deviations.
+template <int ST>
+__device__ __forceinline__ void pull(const IBLB_GLOBAL char *__restrict__ src, uint64_t pb, const RowAddr &ra,
+                                     int x, int nx, float inv, typename Stor<ST>::R (&g)[Q]) {
+    using S = Stor<ST>;
+    pull_raw<ST>(src, pb, ra, x_off<sizeof(typename S::T)>(x, nx), g);
+    if constexpr (S::SCALED) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g[i] *= inv;
     }
 }
 
 // BGK collision with the Guo source (Eqs. 1-6) of one cell in deviation
-// form, given its pulled deviations g and force density F: writes the 19
-// post-collision deviations at byte offset `own` of each plane of dst and
-// returns u (with the half-force correction) and rho.
+// form.  g holds the pulled deviations in stored units (times s for scaled
+// storage), F the force density; out receives the 19 post-collision
+// deviations in stored units, u (with the half-force correction) and rho
+// are returned.
+//
+// Arithmetic: with c_s^2 = 1/3 the post-collision value is
+//   g*_i = (1 - omega) g_i + omega f^eq_i' + S_i,   f^eq_i' = f^eq_i - w_i rho0.
+// Population i and its opposite share c.u and c.F up to sign, so the
+// parts even in c (E_i) and odd in c (O_i) are formed once per pair:
+//   E_i = w_i [omega (drho + rho (4.5 (c.u)^2 - 1.5 u.u)) + guo (9 (c.u)(c.F) - 3 u.F)]
+//   O_i = w_i [3 omega rho (c.u) + 3 guo (c.F)]
+//   g*_i = (1 - omega) g_i + E_i + O_i,  g*_opp = (1 - omega) g_opp + E_i - O_i.
+// Scaled storage multiplies E and O by s (folded into the weights) and
+// divides only the four moments by s.
 template <int ST>
-__device__ __forceinline__ void collide_store(typename Stor<ST>::R (&g)[Q], typename Stor<ST>::R Fx,
-                                              typename Stor<ST>::R Fy, typename Stor<ST>::R Fz,
-                                              typename Stor<ST>::R rho0, typename Stor<ST>::R omega,
-                                              typename Stor<ST>::R guo, IBLB_GLOBAL char *dst,
-                                              uint64_t pb, uint32_t own, float scale,
-                                              typename Stor<ST>::R (&u)[3],
-                                              typename Stor<ST>::R &rho_out) {
+__device__ __forceinline__ void collide(const typename Stor<ST>::R (&g)[Q], typename Stor<ST>::R Fx,
+                                        typename Stor<ST>::R Fy, typename Stor<ST>::R Fz,
+                                        typename Stor<ST>::R rho0, typename Stor<ST>::R omega,
+                                        typename Stor<ST>::R guo, float scale, float inv,
+                                        typename Stor<ST>::R (&out)[Q], typename Stor<ST>::R (&u)[3],
+                                        typename Stor<ST>::R &rho_out) {
     using S = Stor<ST>;
-    using T = typename S::T;
     using R = typename S::R;
-    // moments (Eqs. 5-6): rho = rho0 + sum g, rho u = sum c g + F/2
-    R drho = 0, jx = 0, jy = 0, jz = 0;
+    // moments (Eqs. 5-6) from pair sums and differences
+    R sp[9], dp[9];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        drho += g[i];
-        jx += (R)cx_of(i) * g[i];
-        jy += (R)cy_of(i) * g[i];
-        jz += (R)cz_of(i) * g[i];
+    for (int k = 0; k < 9; ++k) {
+        sp[k] = g[k + 1] + g[k + 10];
+        dp[k] = g[k + 1] - g[k + 10];
+    }
+    R drho = g[0], jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        drho += sp[k];
+        if (cx_of(k + 1) == 1) jx += dp[k];
+        if (cx_of(k + 1) == -1) jx -= dp[k];
+        if (cy_of(k + 1) == 1) jy += dp[k];
+        if (cy_of(k + 1) == -1) jy -= dp[k];
+        if (cz_of(k + 1) == 1) jz += dp[k];
+        if (cz_of(k + 1) == -1) jz -= dp[k];
+    }
+    if constexpr (S::SCALED) {
+        const R iv = (R)inv;
+        drho *= iv;
+        jx *= iv;
+        jy *= iv;
+        jz *= iv;
     }
     const R rho = rho0 + drho;
     const R irho = R(1) / rho;
@@ -222,21 +270,131 @@ __device__ __forceinline__ void collide_store(typename Stor<ST>::R (&g)[Q], type
     const R uz = (jz + R(0.5) * Fz) * irho;
     const R usq = ux * ux + uy * uy + uz * uz;
     const R uF = ux * Fx + uy * Fy + uz * Fz;
+    const R base = omega * (drho - R(1.5) * rho * usq) - R(3) * guo * uF;
+    const R ea = R(4.5) * omega * rho, eb = R(9) * guo;
+    const R oa = R(3) * omega * rho, ob = R(3) * guo;
+    const R omc = R(1) - omega;
+    R w0 = R(1) / R(3), w1 = R(1) / R(18), w2 = R(1) / R(36);
+    if constexpr (S::SCALED) {
+        w0 *= (R)scale;
+        w1 *= (R)scale;
+        w2 *= (R)scale;
+    }
+    out[0] = omc * g[0] + w0 * base;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const R w = (R)w_of(i);
-        const R cu = (R)cx_of(i) * ux + (R)cy_of(i) * uy + (R)cz_of(i) * uz;
-        const R cF = (R)cx_of(i) * Fx + (R)cy_of(i) * Fy + (R)cz_of(i) * Fz;
-        // f_eq - w rho0 (Eq. 3) and the Guo source (Eq. 4), cs^2 = 1/3
-        const R geq = w * (drho + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq));
-        const R src_i = guo * w * (R(3) * (cF - uF) + R(9) * cu * cF);
-        S::st((T *)(IBLB_GLOBAL T *)(dst + (uint64_t)i * pb + own),
-              g[i] + omega * (geq - g[i]) + src_i, scale);
+    for (int k = 0; k < 9; ++k) {
+        const int i = k + 1;
+        const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+        R cu = 0, cF = 0;
+        if (cx == 1) { cu += ux; cF += Fx; }
+        if (cx == -1) { cu -= ux; cF -= Fx; }
+        if (cy == 1) { cu += uy; cF += Fy; }
+        if (cy == -1) { cu -= uy; cF -= Fy; }
+        if (cz == 1) { cu += uz; cF += Fz; }
+        if (cz == -1) { cu -= uz; cF -= Fz; }
+        const R w = (cx * cx + cy * cy + cz * cz) == 1 ? w1 : w2;
+        const R E = w * (cu * (ea * cu + eb * cF) + base);
+        const R O = w * (oa * cu + ob * cF);
+        out[i] = omc * g[i] + (E + O);
+        out[i + 9] = omc * g[i + 9] + (E - O);
     }
     u[0] = ux;
     u[1] = uy;
     u[2] = uz;
     rho_out = rho;
+}
+
+
+// Store the 19 post-collision values at byte offset `own` of each plane.
+template <int ST, bool NT>
+__device__ __forceinline__ void store_ptr(IBLB_GLOBAL char *__restrict__ dst, uint64_t pb, uint32_t own,
+                                          const typename Stor<ST>::R (&out)[Q]) {
+    using S = Stor<ST>;
+    using T = typename S::T;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        IBLB_GLOBAL T *p = (IBLB_GLOBAL T *)(dst + (uint64_t)i * pb + own);
+        if constexpr (NT)
+            S::put_nt(p, out[i]);
+        else
+            S::put(p, out[i]);
+    }
+}
+
+// ------------------------------------------------------- buffer addressing
+// Populations of one buffer through two buffer resources: planes 0..9 from
+// the buffer start and planes 10..18 from plane 10, so that each offset
+// (plane part + row + x, all 32-bit) stays below 4 GiB as long as ten planes
+// do.  In a wave that lies in one row the plane and row parts are scalar
+// (soffset) and only the x part is per lane (voffset).
+constexpr int32_t BUF_WORD3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format
+
+struct PopRes {
+    __amdgpu_buffer_rsrc_t lo, hi;
+};
+__device__ __forceinline__ PopRes pop_res(const void *base, uint64_t pb) {
+    const char *b = (const char *)base;
+    const uint64_t nlo = 10 * pb, nhi = 9 * pb;
+    return {__builtin_amdgcn_make_buffer_rsrc((void *)b, (short)0,
+                                              (int)(uint32_t)(nlo < BUF_MAX_PLANE_GROUP ? nlo : BUF_MAX_PLANE_GROUP),
+                                              BUF_WORD3),
+            __builtin_amdgcn_make_buffer_rsrc((void *)(b + 10 * pb), (short)0, (int)(uint32_t)nhi, BUF_WORD3)};
+}
+
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+template <typename T> __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s);
+template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+}
+template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+}
+template <> __device__ __forceinline__ _Float16 bload<_Float16>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+}
+template <> __device__ __forceinline__ __bf16 bload<__bf16>(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(__bf16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+}
+// aux bit 1 marks the store non-temporal
+template <int AUX> __device__ __forceinline__ void bstore(double x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), r, v, s, AUX);
+}
+template <int AUX> __device__ __forceinline__ void bstore(float x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, AUX);
+}
+template <int AUX> __device__ __forceinline__ void bstore(_Float16 x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, AUX);
+}
+template <int AUX> __device__ __forceinline__ void bstore(__bf16 x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, AUX);
+}
+
+// pull_raw through buffer resources, for a wave whose lanes share `ra`.
+template <int ST>
+__device__ __forceinline__ void pull_buf(const PopRes &rs, uint32_t pb, const RowAddr &ra, const XOff &xo,
+                                         typename Stor<ST>::R (&g)[Q]) {
+    using T = typename Stor<ST>::T;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+        const int o = opp_of(i);
+        const bool bb = (cz == 1 && ra.wlo) || (cz == -1 && ra.whi);
+        const __amdgpu_buffer_rsrc_t r = bb ? (o < 10 ? rs.lo : rs.hi) : (i < 10 ? rs.lo : rs.hi);
+        const uint32_t so = bb ? (uint32_t)(o % 10) * pb + ra.ro[1][1]
+                               : (uint32_t)(i % 10) * pb + ra.ro[cy + 1][cz + 1];
+        const uint32_t vo = bb ? xo.c : (cx == 1 ? xo.m : (cx == -1 ? xo.p : xo.c));
+        g[i] = (typename Stor<ST>::R)bload<T>(r, vo, so);
+    }
+}
+
+// store_ptr through buffer resources; `own_row` is the wave's row offset.
+template <int ST, bool NT>
+__device__ __forceinline__ void store_buf(const PopRes &rd, uint32_t pb, uint32_t own_row, uint32_t xoc,
+                                          const typename Stor<ST>::R (&out)[Q]) {
+    using T = typename Stor<ST>::T;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        bstore<NT ? 2 : 0>((T)out[i], i < 10 ? rd.lo : rd.hi, xoc, (uint32_t)(i % 10) * pb + own_row);
 }
 
 }  // namespace iblb

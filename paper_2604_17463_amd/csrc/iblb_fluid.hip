@@ -12,14 +12,20 @@ namespace iblb {
 // (a row group); threads stride along x so the +-1 shifted loads of a row
 // stay inside one workgroup.  UROW: each wavefront lies in one row
 // (threads_x a multiple of 64), so the row addressing is wave-uniform and
-// lives in scalar registers.  Cells next to a mesh are recomputed by the
-// band kernel afterwards.
-template <int ST, bool UROW>
+// lives in scalar registers.  NT: the populations are written with
+// streaming stores (they are read again only in the next step; pays off
+// once the two population buffers exceed the last-level cache).  Cells
+// next to a mesh are recomputed by the band kernel afterwards.
+template <int ST, bool UROW, bool NT>
 __global__ void __launch_bounds__(K1_MAX_THREADS)
     k_bulk(DevPtrs P, int parity, int full_u, float scale, float inv) {
     using S = Stor<ST>;
     using R = typename S::R;
     constexpr uint32_t EB = sizeof(typename S::T);
+    // 2-byte storage goes through buffer resources (scalar row offsets, one
+    // per-lane offset per access); 4- and 8-byte storage measured faster with
+    // plain global addressing
+    constexpr bool BUF = UROW && EB == 2;
     const int tx = threadIdx.x, ty = threadIdx.y, BX = blockDim.x, BY = blockDim.y;
     const IBLB_CONST RowGroup *rows = (const IBLB_CONST RowGroup *)P.rows;
     for (int gi = blockIdx.x; gi < P.n_rowgroups; gi += gridDim.x) {
@@ -34,15 +40,27 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
         const R gx = (R)B->g[0], gy = (R)B->g[1], gz = (R)B->g[2];
         IBLB_GLOBAL R *__restrict__ uf = (IBLB_GLOBAL R *)B->ufull;
         const uint64_t plane = (uint64_t)B->plane;
-        for (int r0 = rg.r0 + ty; r0 < rg.r1; r0 += BY) {
-            const int r = UROW ? __builtin_amdgcn_readfirstlane(r0) : r0;
-            const int z = r / ny, y = r - z * ny;
-            const RowAddr ra = row_addr(y, z, ny, nz, sx, zper, EB);
+        const PopRes rs = pop_res((const void *)src, pb), rd = pop_res((const void *)dst, pb);
+        // row r = z * ny + y, stepped by BY without a division per row
+        int r = rg.r0 + ty;
+        int z = r / ny, y = r - z * ny;
+        for (; r < rg.r1; r += BY) {
+            const int ry = UROW ? __builtin_amdgcn_readfirstlane(y) : y;
+            const int rz = UROW ? __builtin_amdgcn_readfirstlane(z) : z;
+            const RowAddr ra = row_addr(ry, rz, ny, nz, sx, zper, EB);
             for (int x = tx; x < nx; x += BX) {
-                R g[Q], u[3], rho;
-                pull<ST>(src, pb, ra, x, nx, inv, g);
-                const uint32_t own = ra.ro[1][1] + (uint32_t)x * EB;
-                collide_store<ST>(g, gx, gy, gz, rho0, omega, guo, dst, pb, own, scale, u, rho);
+                R g[Q], out[Q], u[3], rho;
+                const XOff xo = x_off<EB>(x, nx);
+                const uint32_t own = ra.ro[1][1] + xo.c;
+                if constexpr (BUF)
+                    pull_buf<ST>(rs, (uint32_t)pb, ra, xo, g);
+                else
+                    pull_raw<ST>(src, pb, ra, xo, g);
+                collide<ST>(g, gx, gy, gz, rho0, omega, guo, scale, inv, out, u, rho);
+                if constexpr (BUF)
+                    store_buf<ST, NT>(rd, (uint32_t)pb, ra.ro[1][1], xo.c, out);
+                else
+                    store_ptr<ST, NT>(dst, pb, own, out);
                 if (full_u) {
                     const uint64_t e = own / EB;
                     uf[e] = u[0];
@@ -51,6 +69,11 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                 }
                 if (!(rho > R(0) && rho < R(FLT_MAX))) atomicOr(P.status, BIT_RHO);
                 if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > R(1) / R(3)) atomicOr(P.status, BIT_MACH);
+            }
+            y += BY;
+            while (y >= ny) {
+                y -= ny;
+                ++z;
             }
         }
     }
@@ -211,11 +234,13 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
         const IBLB_GLOBAL char *src = (const IBLB_GLOBAL char *)B->f[parity];
         IBLB_GLOBAL char *dst = (IBLB_GLOBAL char *)B->f[parity ^ 1];
         const RowAddr ra = row_addr(cy, cz, B->ny, B->nz, B->sx, B->zbc == 1, EB);
-        R g[Q], u[3], rho;
-        pull<ST>(src, pb, ra, cx, B->nx, inv, g);
-        const uint32_t own = ra.ro[1][1] + (uint32_t)cx * EB;
-        collide_store<ST>(g, (R)B->g[0] + F0, (R)B->g[1] + F1, (R)B->g[2] + F2, (R)B->rho0,
-                          (R)B->omega, (R)B->guo, dst, pb, own, scale, u, rho);
+        R g[Q], out[Q], u[3], rho;
+        const XOff xo = x_off<EB>(cx, B->nx);
+        pull_raw<ST>(src, pb, ra, xo, g);
+        const uint32_t own = ra.ro[1][1] + xo.c;
+        collide<ST>(g, (R)B->g[0] + F0, (R)B->g[1] + F1, (R)B->g[2] + F2, (R)B->rho0, (R)B->omega,
+                    (R)B->guo, scale, inv, out, u, rho);
+        store_ptr<ST, false>(dst, pb, own, out);
         IBLB_GLOBAL R *ub = (IBLB_GLOBAL R *)B->uband + (int64_t)lt * 3 * TILE_CELLS;
         ub[lane] = u[0];
         ub[TILE_CELLS + lane] = u[1];
@@ -321,10 +346,17 @@ static hipError_t launch_bulk_t(const DevPtrs &P, int parity, int full_u, float 
     if (L.bx < 1 || L.by < 1 || L.bx * L.by > K1_MAX_THREADS || L.grid < 1) return hipErrorInvalidValue;
     const dim3 block(L.bx, L.by), grid(L.grid);
     const float inv = 1.0f / scale;
-    if (L.bx % 64 == 0)
-        hipLaunchKernelGGL((k_bulk<ST, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
-    else
-        hipLaunchKernelGGL((k_bulk<ST, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    if (L.bx % 64 == 0) {
+        if (L.nt)
+            hipLaunchKernelGGL((k_bulk<ST, true, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
+        else
+            hipLaunchKernelGGL((k_bulk<ST, true, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    } else {
+        if (L.nt)
+            hipLaunchKernelGGL((k_bulk<ST, false, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
+        else
+            hipLaunchKernelGGL((k_bulk<ST, false, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    }
     return hipGetLastError();
 }
 

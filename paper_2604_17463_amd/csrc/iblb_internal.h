@@ -51,6 +51,10 @@ __host__ __device__ constexpr double w_of(int i) {
                          : 1.0 / 36.0);
 }
 
+// Ten population planes of a box are addressed with 32-bit offsets from one
+// base: their bytes may not exceed this.
+constexpr int64_t BUF_MAX_PLANE_GROUP = 0xFFFFFFFFll;
+
 enum : uint32_t { BIT_RHO = 1u, BIT_MACH = 2u, BIT_WALL = 4u, BIT_JUMP = 8u };
 
 struct BoxDev {
@@ -121,6 +125,7 @@ struct DevPtrs {
 struct Launch {
     int bx, by;                 // bulk stream-collide block shape
     int grid;                   // bulk stream-collide grid (<= n_rowgroups)
+    int nt;                     // bulk stream-collide writes with streaming stores
 };
 
 hipError_t launch_tri(const DevPtrs &P, bool f64, hipStream_t s);

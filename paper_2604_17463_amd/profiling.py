@@ -20,10 +20,10 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--storage", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--launch-spreading", type=int, nargs=2, default=(128, 1),
-                    help="threads_x rows of the bulk launch on the spreading workload")
-    ap.add_argument("--launch-box", type=int, nargs=2, default=(256, 1),
-                    help="threads_x rows of the bulk launch on the 256x256x128 box")
+    ap.add_argument("--launch-spreading", type=int, nargs=3, default=(128, 1, 0),
+                    help="threads_x rows streaming_stores of the bulk launch on the spreading workload")
+    ap.add_argument("--launch-box", type=int, nargs=3, default=(256, 1, 1),
+                    help="threads_x rows streaming_stores of the bulk launch on the 256x256x128 box")
     args = ap.parse_args()
     import torch
 

@@ -76,6 +76,17 @@ def test_rejects_bad_box_parameters():
     assert _err(wl) == B.IBLB_E_INVAL
     wl = configs.plain_c1()
     assert _err(wl, storage=7) == B.IBLB_E_INVAL
+
+
+def test_box_size_limit_of_the_stream_collide_addressing():
+    # ten population planes are addressed with 32-bit offsets from one base
+    from iblb_inputs.configs import Box, Workload
+    ok = Workload("ok", [Box(512, 512, 256, tau=0.9)], [])         # 67 M cells, 2.7 GB per ten FP32 planes
+    assert P.workspace_size(P.make_config(ok, storage=B.IBLB_F32)[0]) > 0
+    big = Workload("big", [Box(512, 512, 512, tau=0.9)], [])       # 134 M cells: 5.4 GB per ten FP32 planes
+    assert _err(big, storage=B.IBLB_F32) == B.IBLB_E_INVAL
+    assert P.workspace_size(P.make_config(big, storage=B.IBLB_F16DEV, dev_scale=4096.0)[0]) > 0
+    assert _err(ok, storage=B.IBLB_F64) == B.IBLB_E_INVAL   # 5.4 GB per ten FP64 planes
     assert _err(configs.plain_c1(), storage=B.IBLB_F16DEV, dev_scale=3.0) == B.IBLB_E_INVAL
 
 

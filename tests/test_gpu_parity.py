@@ -329,8 +329,13 @@ def test_set_launch_rejects_shapes_beyond_the_kernel_bound():
         with pytest.raises(P.IblbError) as e:
             s.set_launch(bx, by)
         assert e.value.code == -1
+    with pytest.raises(P.IblbError) as e:
+        s.set_launch(64, 4, 2)
+    assert e.value.code == -1
     s.set_launch(64, 4)
-    assert s.get_launch() == (64, 4)
+    assert s.get_launch() == (64, 4, 0)
+    s.set_launch(64, 4, 1)
+    assert s.get_launch() == (64, 4, 1)
     s.step(3)
 
 
