@@ -298,14 +298,14 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
     p.off_phi = take(3 * N * p.real);
     p.off_wgt = take(12 * N * p.real);
     p.off_trec = take((size_t)TREC * p.Ttot * p.real);
-    p.off_tile_list = take((size_t)p.total_tiles * 4);
+    p.off_tile_list = take((size_t)p.total_tiles * 8);
     p.off_tile_count = take(2 * 4);
     p.off_base = take(3 * N * 4);
     p.off_s0 = take(3 * N * 4);
     p.off_bbox = take(6 * (size_t)p.nblk * 4);
     p.off_breg = take((size_t)BREG * p.nblk * 4);
     p.off_part = take((size_t)3 * MAXP * p.nblk * p.real);
-    p.off_blk_drop = take((size_t)p.nblk * 4);
+    p.off_blk_drop = take((size_t)p.nblk * 8);
     p.off_tri = take(3 * (size_t)p.Ttot * 4);
     p.off_csr_off = take((N + 1) * 4);
     p.off_csr_ent = take(3 * (size_t)p.Ttot * 4);
@@ -694,7 +694,7 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     const int R = p.real;
     std::vector<char> qh((size_t)3 * N * R, 0), ql((size_t)3 * N * R, 0);
     std::vector<int32_t> tri((size_t)3 * std::max(p.Ttot, 1)), csr_off((size_t)N + 1, 0),
-        csr_ent((size_t)3 * std::max(p.Ttot, 1)), blk_drop(std::max(p.nblk, 1));
+        csr_ent((size_t)3 * std::max(p.Ttot, 1)), blk_drop(2 * (size_t)std::max(p.nblk, 1));
     std::vector<TriChunk> chunks(std::max(p.n_chunks, 1));
     std::vector<DropDev> dd(std::max<size_t>(p.drops.size(), 1));
     for (size_t di = 0; di < p.drops.size(); ++di) {
@@ -717,7 +717,10 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
         D.kvol = H.d.k_vol;
         D.V0 = 0.0;
         for (int a = 0; a < 3; ++a) D.ref[a] = H.ref[a];
-        for (int k = 0; k < H.n_blocks; ++k) blk_drop[H.blk_off + k] = (int32_t)di;
+        for (int k = 0; k < H.n_blocks; ++k) {
+            blk_drop[2 * (H.blk_off + k)] = (int32_t)di;
+            blk_drop[2 * (H.blk_off + k) + 1] = (int32_t)H.d.box;
+        }
         for (int k = 0; k < H.n_chunks; ++k) {
             const int t0 = H.tri_off + k * TRI_CHUNK;
             chunks[H.chunk_off + k] = {(int32_t)di, t0, std::min(t0 + TRI_CHUNK, H.tri_off + H.d.n_tris), 0};
@@ -758,7 +761,7 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     HIPCHK(c, hipMemcpyAsync(P.tri, tri.data(), 3 * (size_t)p.Ttot * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(P.csr_off, csr_off.data(), csr_off.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(P.csr_ent, csr_ent.data(), 3 * (size_t)p.Ttot * 4, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(P.blk_drop, blk_drop.data(), (size_t)p.nblk * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(P.blk_drop, blk_drop.data(), (size_t)p.nblk * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(P.chunks, chunks.data(), (size_t)p.n_chunks * sizeof(TriChunk), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(P.tchunk_box, tchunk.data(), tchunk.size() * 4, hipMemcpyHostToDevice, c->stream));
     // fluid at rest: all deviations zero; no tile stamped; band zeroed

@@ -64,16 +64,21 @@ template <typename V> __device__ __forceinline__ V wave_sum(V v) {
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
+// Minimum / maximum over the 64 lanes of a wave whose lanes are all active:
+// rotate-and-combine inside each row of 16 lanes (DPP row_ror 8, 4, 2, 1:
+// no LDS round trip), then combine the four row results as scalars.
+template <bool MAX> __device__ __forceinline__ int wave_minmax(int v) {
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x124, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x122, 0xf, 0xf, false));
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x121, 0xf, 0xf, false));
+    const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+    return op(op(r0, r1), op(r2, r3));
 }
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
+__device__ __forceinline__ int wave_min(int v) { return wave_minmax<false>(v); }
+__device__ __forceinline__ int wave_max(int v) { return wave_minmax<true>(v); }
 
 // Value of v in lane l (l wave-uniform), as a scalar.
 template <typename R> __device__ __forceinline__ R bcast(R v, int l);

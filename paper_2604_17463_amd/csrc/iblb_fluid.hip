@@ -84,41 +84,57 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
 // [y0..y1] x [z0..z1], for the calling lane.  Node blocks whose stencil box
 // meets the tile contribute in ascending block order; a block's own
 // contribution is the partial sum its node pass accumulated over its nodes
-// in ascending order (read from the block's partial region), or, for a
-// block whose region did not fit, the nodes summed here one by one in the
-// same order.  No atomics: the sum order per cell is fixed.
+// (read from the block's partial region), or, for a block whose region did
+// not fit, the nodes summed here one by one in ascending order.  No
+// atomics: the sum order per cell is fixed.
+//
+// Latency: the bounding boxes of GATHER_GROUP x 64 blocks are tested with
+// their loads in flight together; the hits go to a wave-private LDS list in
+// ascending order and are then read back eight at a time, so region
+// descriptors and partial values of eight blocks load side by side.
+constexpr int GATHER_GROUP = 4;
+
 template <typename R>
 __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxDev *B, int x0, int x1,
                                          int y0, int y1, int z0, int z1, int cx, int cy, int cz,
-                                         R &F0, R &F1, R &F2) {
+                                         int *hits, R &F0, R &F1, R &F2) {
     const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
     const int nb = P.nblk, N = P.Ntot;
     const bool zper = B->zbc == 1;
     const int nx = B->nx, ny = B->ny, nz = B->nz;
+    const int b0 = B->blk_begin, b1 = B->blk_end;
     const IBLB_GLOBAL R *part = (const IBLB_GLOBAL R *)P.part;
     const IBLB_CONST int32_t *breg = (const IBLB_CONST int32_t *)P.breg;
-    for (int kb = B->blk_begin; kb < B->blk_end; kb += 64) {
-        const int mb = kb + lane;
-        bool hit = false;
-        if (mb < B->blk_end)
-            hit = meets(P.bbox[0 * nb + mb], P.bbox[1 * nb + mb], x0, x1, nx, true) &&
-                  meets(P.bbox[2 * nb + mb], P.bbox[3 * nb + mb], y0, y1, ny, true) &&
-                  meets(P.bbox[4 * nb + mb], P.bbox[5 * nb + mb], z0, z1, nz, zper);
-        uint64_t bmask = __ballot(hit);
-        while (bmask) {
-            // up to four candidate blocks per round: their loads are issued
-            // together, their sums added in block order
-            int ids[4], n = 0;
+    for (int kb = b0; kb < b1; kb += 64 * GATHER_GROUP) {
+        bool hit[GATHER_GROUP];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (bmask) {
-                    ids[n++] = kb + __builtin_ctzll(bmask);
-                    bmask &= bmask - 1;
-                }
-            R v[4][3];
-            bool ovf[4];
+        for (int g = 0; g < GATHER_GROUP; ++g) {
+            const int mb = kb + 64 * g + lane;
+            hit[g] = mb < b1 &&
+                     meets(P.bbox[0 * nb + mb], P.bbox[1 * nb + mb], x0, x1, nx, true) &&
+                     meets(P.bbox[2 * nb + mb], P.bbox[3 * nb + mb], y0, y1, ny, true) &&
+                     meets(P.bbox[4 * nb + mb], P.bbox[5 * nb + mb], z0, z1, nz, zper);
+        }
+        int total = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+        for (int g = 0; g < GATHER_GROUP; ++g) {
+            const uint64_t m = __ballot(hit[g]);
+            if (hit[g]) hits[total + __popcll(m & below)] = kb + 64 * g + lane;
+            total += __popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int k0 = 0; k0 < total; k0 += 8) {
+            const int n = min(8, total - k0);
+            int ids[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) ids[k] = __builtin_amdgcn_readfirstlane(k < n ? hits[k0 + k] : 0);
+            R v[8][3];
+            bool ovf[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
                 v[k][0] = v[k][1] = v[k][2] = R(0);
                 ovf[k] = false;
                 if (k < n) {
@@ -140,7 +156,7 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
                 }
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int k = 0; k < 8; ++k) {
                 if (k >= n) break;
                 if (!ovf[k]) {
                     F0 += v[k][0];
@@ -150,7 +166,7 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
                 }
                 // block without a partial region: its nodes one by one
                 const int blk = ids[k];
-                const DropDev &D = P.drops[P.blk_drop[blk]];
+                const DropDev &D = P.drops[P.blk_drop[2 * blk]];
                 const int j = blk * NB + lane;
                 bool nh = false;
                 if (j - D.node_off < D.n_nodes) {
@@ -193,6 +209,7 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
                 }
             }
         }
+        __builtin_amdgcn_wave_barrier();  // the list is rewritten by the next group
     }
 }
 
@@ -206,22 +223,38 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
     using S = Stor<ST>;
     using R = typename S::R;
     constexpr uint32_t EB = sizeof(typename S::T);
+    __shared__ int hits[4][64 * GATHER_GROUP];
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int nwaves = gridDim.x * 4;
-    const int ctr = *P.ctr;
-    const int count = P.tile_count[ctr & 1];
+    // the epoch counter and both list lengths in one round trip
+    const int ctr = *P.ctr, n0 = P.tile_count[0], n1 = P.tile_count[1];
+    const int count = (ctr & 1) ? n1 : n0;
+    const IBLB_CONST int32_t *tl = (const IBLB_CONST int32_t *)P.tile_list;
     for (int i = wave; i < count; i += nwaves) {
-        const int gt = P.tile_list[i];
-        const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + P.tchunk_box[gt / TILE_CELLS];
+        const int gt = tl[2 * i];  // global tile id and its box
+        const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + tl[2 * i + 1];
         const int lt = gt - B->tile_base;
         const int tx = lt % B->tnx, ty = (lt / B->tnx) % B->tny, tz = lt / (B->tnx * B->tny);
         const int x0 = tx * TILE, y0 = ty * TILE, z0 = tz * TILE;
         const int x1 = min(x0 + TILE - 1, B->nx - 1), y1 = min(y0 + TILE - 1, B->ny - 1),
                   z1 = min(z0 + TILE - 1, B->nz - 1);
         const int cx = x0 + (lane & 3), cy = y0 + ((lane >> 2) & 3), cz = z0 + (lane >> 4);
+        const bool inside = cx < B->nx && cy < B->ny && cz < B->nz;
+        // the populations are pulled first so that their loads are in flight
+        // during the force gather
+        const uint64_t pb = (uint64_t)B->plane * EB;
+        const IBLB_GLOBAL char *src = (const IBLB_GLOBAL char *)B->f[parity];
+        RowAddr ra{};
+        XOff xo{};
+        R g[Q];
+        if (COLLIDE && inside) {
+            ra = row_addr(cy, cz, B->ny, B->nz, B->sx, B->zbc == 1, EB);
+            xo = x_off<EB>(cx, B->nx);
+            pull_raw<ST>(src, pb, ra, xo, g);
+        }
         R F0 = 0, F1 = 0, F2 = 0;
-        gather_F<R>(P, B, x0, x1, y0, y1, z0, z1, cx, cy, cz, F0, F1, F2);
+        gather_F<R>(P, B, x0, x1, y0, y1, z0, z1, cx, cy, cz, hits[threadIdx.x >> 6], F0, F1, F2);
         if (!COLLIDE) {
             IBLB_GLOBAL R *Fb = (IBLB_GLOBAL R *)B->Fband + (int64_t)lt * 3 * TILE_CELLS;
             Fb[lane] = F0;
@@ -229,14 +262,9 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
             Fb[2 * TILE_CELLS + lane] = F2;
             continue;
         }
-        if (cx >= B->nx || cy >= B->ny || cz >= B->nz) continue;
-        const uint64_t pb = (uint64_t)B->plane * EB;
-        const IBLB_GLOBAL char *src = (const IBLB_GLOBAL char *)B->f[parity];
+        if (!inside) continue;
         IBLB_GLOBAL char *dst = (IBLB_GLOBAL char *)B->f[parity ^ 1];
-        const RowAddr ra = row_addr(cy, cz, B->ny, B->nz, B->sx, B->zbc == 1, EB);
-        R g[Q], out[Q], u[3], rho;
-        const XOff xo = x_off<EB>(cx, B->nx);
-        pull_raw<ST>(src, pb, ra, xo, g);
+        R out[Q], u[3], rho;
         const uint32_t own = ra.ro[1][1] + xo.c;
         collide<ST>(g, (R)B->g[0] + F0, (R)B->g[1] + F1, (R)B->g[2] + F2, (R)B->rho0, (R)B->omega,
                     (R)B->guo, scale, inv, out, u, rho);

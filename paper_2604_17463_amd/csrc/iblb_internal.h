@@ -97,7 +97,7 @@ struct DevPtrs {
     void *qh, *ql;              // position, high and low parts (Real)
     void *phi;                  // nodal force (Real)
     void *trec;                 // [Ttot][TREC] per-triangle records (Real)
-    int32_t *tile_list;         // stamped tiles of the current epoch (global ids)
+    int32_t *tile_list;         // [total_tiles][2]: stamped tiles of the epoch (global id, box)
     int32_t *tile_count;        // [2] list lengths, indexed by epoch parity
     void *wgt;                  // [12][Ntot] Peskin weights x0..3,y0..3,z0..3 (Real)
     int32_t *base;              // floor(q - 1/2), unwrapped
@@ -105,7 +105,7 @@ struct DevPtrs {
     int32_t *bbox;              // [6][nblk]: x0,x1,y0,y1,z0,z1 of stencil cells
     int32_t *breg;              // [nblk][BREG]: partial region x0,y0,z0 (wrapped), ex,ey,ez, overflow
     void *part;                 // [nblk][3][MAXP] partial spread regions (Real)
-    int32_t *blk_drop;          // [nblk]
+    int32_t *blk_drop;          // [nblk][2]: droplet and box of each node block
     int32_t *tri;               // [Ttot][3] global node ids
     int32_t *csr_off;           // [Ntot+1]
     int32_t *csr_ent;           // [3 Ttot]: 3*t + corner

@@ -107,203 +107,237 @@ __global__ void __launch_bounds__(64) k_set_v0(DevPtrs P) {
 // from LDS as broadcasts), then writes that partial region out for the tile
 // gather.
 template <typename R>
-__global__ void __launch_bounds__(64) k_node(DevPtrs P, int mode) {
-    __shared__ R reg[3 * MAXP];
+__global__ void __launch_bounds__(256) k_node(DevPtrs P, int mode) {
+    // NR waves spread NB / NR nodes each into their own LDS copy of the region
+    constexpr int NR = sizeof(R) == 4 ? 4 : 2;
+    __shared__ R reg[NR][3 * MAXP];
     __shared__ R nw[12][NB], nf[3][NB];
     __shared__ int nbs[3][NB];
-    const int lane = threadIdx.x;
+    __shared__ int sreg[5];  // ex, ey, ez, overflow, nodes in the block
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int blk = blockIdx.x;
-    const int d = P.blk_drop[blk];
+    // droplet and box in one load, so their records load side by side
+    const int d = P.blk_drop[2 * blk], bi = P.blk_drop[2 * blk + 1];
     const DropDev &D = P.drops[d];
-    const BoxDev &B = P.boxes[D.box];
-    const int N = P.Ntot;
-    const R *qh = (const R *)P.qh, *ql = (const R *)P.ql;
-    using V4 = typename Vec4<R>::T;
-    const V4 *tr = (const V4 *)P.trec;
-    const int j = blk * NB + lane;
-    const bool valid = (j - D.node_off) < D.n_nodes;
-    const bool zper = B.zbc == 1;
-    const int dims[3] = {B.nx, B.ny, B.nz};
-    double dV = 0.0;
-    if (D.kvol > 0.0) {
-        const double V = droplet_partial_sum(P.tri_part, D.chunk_off, D.n_chunks, lane);
-        dV = (V - D.V0) / D.V0;
-    }
-    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
-    R w[12], f[3];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) w[k] = 0;
-    f[0] = f[1] = f[2] = 0;
-    int b[3] = {0, 0, 0};
-    if (valid) {
-        const Node3<R> qj = load_node(qh, ql, N, j);
-        R st[3] = {0, 0, 0}, ns[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
-        R chi = 0;
-        const int e0 = P.csr_off[j], e1 = P.csr_off[j + 1];
-        for (int e = e0; e < e1; e += 8) {
-            int code[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) code[k] = e + k < e1 ? P.csr_ent[e + k] : -1;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (code[k] < 0) continue;
-                const int t = code[k] / 3, c = code[k] - 3 * t;
-                const V4 r0 = tr[(int64_t)t * (TREC / 4)];
-                const V4 r1 = tr[(int64_t)t * (TREC / 4) + 1];
-                const V4 rf = tr[(int64_t)t * (TREC / 4) + 2 + c];
-                chi += r0.x;
-                ns[0] += r0.y;
-                ns[1] += r0.z;
-                ns[2] += r0.w;
-                gv[0] += r1.x;
-                gv[1] += r1.y;
-                gv[2] += r1.z;
-                st[0] += rf.x;
-                st[1] += rf.y;
-                st[2] += rf.z;
-            }
+    if (wave == 0) {  // the node pass: one lane per node
+        const BoxDev &B = P.boxes[bi];
+        // every constant of the droplet and its box is read here, before the
+        // first store (a scalar load behind vector stores waits for them)
+        const int nx = B.nx, ny = B.ny, nz = B.nz, tnx = B.tnx, tny = B.tny;
+        const bool zper = B.zbc == 1;
+        IBLB_GLOBAL int32_t *const stamp = (IBLB_GLOBAL int32_t *)B.stamp;
+        const int node_off = D.node_off, n_nodes = D.n_nodes, n_exp = D.n_exp, m_exp = D.m_exp;
+        const int chunk_off = D.chunk_off, n_chunks = D.n_chunks;
+        const double kvol = D.kvol, V0 = D.V0, Aw = D.A, xi = D.xi;
+        const int N = P.Ntot;
+        const R *qh = (const R *)P.qh, *ql = (const R *)P.ql;
+        using V4 = typename Vec4<R>::T;
+        const V4 *tr = (const V4 *)P.trec;
+        const int j = blk * NB + lane;
+        const bool valid = (j - node_off) < n_nodes;
+        const int dims[3] = {nx, ny, nz};
+        const int ctr = mode == 0 ? *P.ctr : 0;
+        double dV = 0.0;
+        if (kvol > 0.0) {
+            const double V = droplet_partial_sum(P.tri_part, chunk_off, n_chunks, lane);
+            dV = (V - V0) / V0;
         }
-        const R nl = R(1) / sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);
-        const R dist = qj.h[2] + qj.l[2];
-        if (!(dist > R(0))) atomicOr(P.status, BIT_WALL);
-        const R rr = (R)D.xi / dist;
-        R pn = 1, pm = 1;
-        for (int k = 0; k < D.n_exp; ++k) pn *= rr;
-        for (int k = 0; k < D.m_exp; ++k) pm *= rr;
-        const R Pi = (R)D.A * (pn - pm);
-        const R kw = chi * Pi / R(3) * nl;
-        const R kv = (R)(-D.kvol * dV);
-        R *phi = (R *)P.phi;
+        int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+        R w[12], f[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            f[k] = st[k] - kw * ns[k] + kv * gv[k];
-            phi[k * N + j] = f[k];
-        }
-
-        // base cell and Peskin 4-point weights per axis.  With t = q - b - 1/2
-        // in [0,1] all four weights share s = sqrt(1 + 4t(1-t)):
-        //   b-1: (3 - 2t - s)/8, b: (3 - 2t + s)/8, b+1: (1 + 2t + s)/8,
-        //   b+2: (1 + 2t - s)/8.
-        R *wg = (R *)P.wgt;
+        for (int k = 0; k < 12; ++k) w[k] = 0;
+        f[0] = f[1] = f[2] = 0;
+        int b[3] = {0, 0, 0};
+        if (valid) {
+            const Node3<R> qj = load_node(qh, ql, N, j);
+            R st[3] = {0, 0, 0}, ns[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
+            R chi = 0;
+            const int e0 = P.csr_off[j], e1 = P.csr_off[j + 1];
+            for (int e = e0; e < e1; e += 8) {
+                int code[8];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            R qa = qj.h[a], la = qj.l[a];
-            if (!(fabs(qa) < R(1.0e7))) {  // non-finite or absurd: flag, keep indices sane
-                atomicOr(P.status, BIT_JUMP);
-                qa = R(0.5);
-                la = R(0);
-            }
-            const R fl = floor(qa);
-            const R rf = (qa - fl - R(0.5)) + la;
-            const bool neg = rf < R(0);
-            b[a] = (int)fl - (neg ? 1 : 0);
-            const R t = neg ? rf + R(1) : rf;
-            const R s = sqrt(R(1) + R(4) * t * (R(1) - t));
-            w[4 * a + 0] = (R(3) - R(2) * t - s) * R(0.125);
-            w[4 * a + 1] = (R(3) - R(2) * t + s) * R(0.125);
-            w[4 * a + 2] = (R(1) + R(2) * t + s) * R(0.125);
-            w[4 * a + 3] = (R(1) + R(2) * t - s) * R(0.125);
+                for (int k = 0; k < 8; ++k) code[k] = e + k < e1 ? P.csr_ent[e + k] : -1;
 #pragma unroll
-            for (int o = 0; o < 4; ++o) wg[(4 * a + o) * N + j] = w[4 * a + o];
-            P.base[a * N + j] = b[a];
-            const bool per = a < 2 || zper;
-            P.s0[a * N + j] = per ? wrapn(b[a] - 1, dims[a]) : b[a] - 1;
-            lo[a] = b[a] - 1;
-            hi[a] = b[a] + 2;
-        }
-        if (mode == 0) {
-            // epoch stamp of every tile holding a stencil cell (same value
-            // from every writer, so plain stores)
-            const int ctr = *P.ctr;
-            int tl[3][4], tn[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                tn[a] = 0;
-                const bool per = a < 2 || zper;
-                for (int o = 0; o < 4; ++o) {
-                    int c = lo[a] + o;
-                    if (per) c = wrapn(c, dims[a]);
-                    else if (c < 0 || c >= dims[a]) continue;
-                    const int tt = c >> 2;
-                    if (tn[a] == 0 || tl[a][tn[a] - 1] != tt) tl[a][tn[a]++] = tt;
+                for (int k = 0; k < 8; ++k) {
+                    if (code[k] < 0) continue;
+                    const int t = code[k] / 3, c = code[k] - 3 * t;
+                    const V4 r0 = tr[(int64_t)t * (TREC / 4)];
+                    const V4 r1 = tr[(int64_t)t * (TREC / 4) + 1];
+                    const V4 rf = tr[(int64_t)t * (TREC / 4) + 2 + c];
+                    chi += r0.x;
+                    ns[0] += r0.y;
+                    ns[1] += r0.z;
+                    ns[2] += r0.w;
+                    gv[0] += r1.x;
+                    gv[1] += r1.y;
+                    gv[2] += r1.z;
+                    st[0] += rf.x;
+                    st[1] += rf.y;
+                    st[2] += rf.z;
                 }
             }
-            for (int iz = 0; iz < tn[2]; ++iz)
-                for (int iy = 0; iy < tn[1]; ++iy)
-                    for (int ix = 0; ix < tn[0]; ++ix)
-                        ((IBLB_GLOBAL int32_t *)B.stamp)[((int64_t)tl[2][iz] * B.tny + tl[1][iy]) *
-                                                              B.tnx + tl[0][ix]] = ctr;
-        }
-    }
-    // stencil bounding box of the block (unwrapped cell indices)
-    int bl[3], bh[3];
+            const R nl = R(1) / sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);
+            const R dist = qj.h[2] + qj.l[2];
+            if (!(dist > R(0))) atomicOr(P.status, BIT_WALL);
+            const R rr = (R)xi / dist;
+            R pn = 1, pm = 1;
+            for (int k = 0; k < n_exp; ++k) pn *= rr;
+            for (int k = 0; k < m_exp; ++k) pm *= rr;
+            const R Pi = (R)Aw * (pn - pm);
+            const R kw = chi * Pi / R(3) * nl;
+            const R kv = (R)(-kvol * dV);
+            R *phi = (R *)P.phi;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        bl[a] = wave_min(lo[a]);
-        bh[a] = wave_max(hi[a]);
+            for (int k = 0; k < 3; ++k) {
+                f[k] = st[k] - kw * ns[k] + kv * gv[k];
+                phi[k * N + j] = f[k];
+            }
+
+            // base cell and Peskin 4-point weights per axis.  With t = q - b - 1/2
+            // in [0,1] all four weights share s = sqrt(1 + 4t(1-t)):
+            //   b-1: (3 - 2t - s)/8, b: (3 - 2t + s)/8, b+1: (1 + 2t + s)/8,
+            //   b+2: (1 + 2t - s)/8.
+            R *wg = (R *)P.wgt;
+            int s0[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                R qa = qj.h[a], la = qj.l[a];
+                if (!(fabs(qa) < R(1.0e7))) {  // non-finite or absurd: flag, keep indices sane
+                    atomicOr(P.status, BIT_JUMP);
+                    qa = R(0.5);
+                    la = R(0);
+                }
+                const R fl = floor(qa);
+                const R rf = (qa - fl - R(0.5)) + la;
+                const bool neg = rf < R(0);
+                b[a] = (int)fl - (neg ? 1 : 0);
+                const R t = neg ? rf + R(1) : rf;
+                const R s = sqrt(R(1) + R(4) * t * (R(1) - t));
+                w[4 * a + 0] = (R(3) - R(2) * t - s) * R(0.125);
+                w[4 * a + 1] = (R(3) - R(2) * t + s) * R(0.125);
+                w[4 * a + 2] = (R(1) + R(2) * t + s) * R(0.125);
+                w[4 * a + 3] = (R(1) + R(2) * t - s) * R(0.125);
+#pragma unroll
+                for (int o = 0; o < 4; ++o) wg[(4 * a + o) * N + j] = w[4 * a + o];
+                P.base[a * N + j] = b[a];
+                const bool per = a < 2 || zper;
+                s0[a] = per ? wrapn(b[a] - 1, dims[a]) : b[a] - 1;
+                P.s0[a * N + j] = s0[a];
+                lo[a] = b[a] - 1;
+                hi[a] = b[a] + 2;
+            }
+            if (mode == 0) {
+                // epoch stamp of every tile holding a stencil cell (same value
+                // from every writer, so plain stores)
+                int tl[3][4], tn[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    tn[a] = 0;
+                    const bool per = a < 2 || zper;
+                    for (int o = 0; o < 4; ++o) {
+                        int c = s0[a] + o;  // s0 is wrapped on periodic axes
+                        if (per) c = c >= dims[a] ? c - dims[a] : c;
+                        else if (c < 0 || c >= dims[a]) continue;
+                        const int tt = c >> 2;
+                        if (tn[a] == 0 || tl[a][tn[a] - 1] != tt) tl[a][tn[a]++] = tt;
+                    }
+                }
+                for (int iz = 0; iz < tn[2]; ++iz)
+                    for (int iy = 0; iy < tn[1]; ++iy)
+                        for (int ix = 0; ix < tn[0]; ++ix)
+                            stamp[((int64_t)tl[2][iz] * tny + tl[1][iy]) * tnx + tl[0][ix]] = ctr;
+            }
+        }
+        // stencil bounding box of the block (unwrapped cell indices)
+        int bl[3], bh[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            bl[a] = wave_min(lo[a]);
+            bh[a] = wave_max(hi[a]);
+            if (lane == 0) {
+                P.bbox[(2 * a) * P.nblk + blk] = bl[a];
+                P.bbox[(2 * a + 1) * P.nblk + blk] = bh[a];
+            }
+        }
+        if (mode != 0) return;
+        // partial spread over the block's stencil box
+        int zl = bl[2], zh = bh[2];
+        if (!zper) {
+            zl = max(zl, 0);
+            zh = min(zh, nz - 1);
+        }
+        const int ex = bh[0] - bl[0] + 1, ey = bh[1] - bl[1] + 1, ez = zh - zl + 1;
+        const bool ovf = ex > nx || ey > ny || (zper && ez > nz) || ez < 1 ||
+                         (int64_t)ex * ey * ez > MAXP;
         if (lane == 0) {
-            P.bbox[(2 * a) * P.nblk + blk] = bl[a];
-            P.bbox[(2 * a + 1) * P.nblk + blk] = bh[a];
+            int32_t *br = P.breg + (int64_t)blk * BREG;
+            br[0] = wrapn(bl[0], nx);
+            br[1] = wrapn(bl[1], ny);
+            br[2] = zper ? wrapn(zl, nz) : zl;
+            br[3] = ex;
+            br[4] = ey;
+            br[5] = ez;
+            br[6] = ovf ? 1 : 0;
+            br[7] = 0;
+            sreg[0] = ex;
+            sreg[1] = ey;
+            sreg[2] = ez;
+            sreg[3] = ovf ? 1 : 0;
+            sreg[4] = min(NB, n_nodes - (blk * NB - node_off));
         }
-    }
+        // the block's node data, read back by the spreading waves as broadcasts
+#pragma unroll
+        for (int k = 0; k < 12; ++k) nw[k][lane] = w[k];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            nf[k][lane] = f[k];
+            nbs[k][lane] = b[k] - 1 - (k == 0 ? bl[0] : (k == 1 ? bl[1] : zl));
+        }
+    }  // wave 0
     if (mode != 0) return;
-    // partial spread over the block's stencil box
-    int zl = bl[2], zh = bh[2];
-    if (!zper) {
-        zl = max(zl, 0);
-        zh = min(zh, B.nz - 1);
-    }
-    const int ex = bh[0] - bl[0] + 1, ey = bh[1] - bl[1] + 1, ez = zh - zl + 1;
-    const bool ovf = ex > B.nx || ey > B.ny || (zper && ez > B.nz) || ez < 1 ||
-                     (int64_t)ex * ey * ez > MAXP;
-    if (lane == 0) {
-        int32_t *br = P.breg + (int64_t)blk * BREG;
-        br[0] = wrapn(bl[0], B.nx);
-        br[1] = wrapn(bl[1], B.ny);
-        br[2] = zper ? wrapn(zl, B.nz) : zl;
-        br[3] = ex;
-        br[4] = ey;
-        br[5] = ez;
-        br[6] = ovf ? 1 : 0;
-        br[7] = 0;
-    }
-    if (ovf) return;
-    const int ncell = ex * ey * ez;
-    for (int c = lane; c < ncell; c += 64) {
-        reg[c] = R(0);
-        reg[MAXP + c] = R(0);
-        reg[2 * MAXP + c] = R(0);
-    }
-    // the block's node data, read back by every lane as broadcasts
-#pragma unroll
-    for (int k = 0; k < 12; ++k) nw[k][lane] = w[k];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        nf[k][lane] = f[k];
-        nbs[k][lane] = b[k] - 1 - (k == 0 ? bl[0] : (k == 1 ? bl[1] : zl));
-    }
     __syncthreads();
-    const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
-    const int nvalid = min(NB, D.n_nodes - (blk * NB - D.node_off));
-    for (int nl = 0; nl < nvalid; ++nl) {
-        const int rz = nbs[2][nl] + oz;  // region coordinates of this lane's stencil cell
-        const int ry = nbs[1][nl] + oy;
-        const int rx = nbs[0][nl] + ox;
-        const R wv = nw[ox][nl] * nw[4 + oy][nl] * nw[8 + oz][nl];
-        if (rz >= 0 && rz < ez) {  // outside only for wall layers (dropped)
-            const int c = (rz * ey + ry) * ex + rx;
-            reg[c] += nf[0][nl] * wv;
-            reg[MAXP + c] += nf[1][nl] * wv;
-            reg[2 * MAXP + c] += nf[2][nl] * wv;
+    const int ex = sreg[0], ey = sreg[1], ez = sreg[2];
+    if (sreg[3]) return;
+    const int ncell = ex * ey * ez, nvalid = sreg[4];
+    for (int c = tid; c < ncell; c += 256)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            reg[r][c] = R(0);
+            reg[r][MAXP + c] = R(0);
+            reg[r][2 * MAXP + c] = R(0);
+        }
+    __syncthreads();
+    // wave r < NR adds nodes [r NB/NR, (r+1) NB/NR) in ascending order; each
+    // lane is one of a node's 64 stencil points, so no two lanes of a wave
+    // touch the same cell
+    if (wave < NR) {
+        const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
+        R *rg = reg[wave];
+        const int n1 = min((wave + 1) * (NB / NR), nvalid);
+        for (int nl = wave * (NB / NR); nl < n1; ++nl) {
+            const int rz = nbs[2][nl] + oz;  // region coordinates of this lane's stencil cell
+            const int ry = nbs[1][nl] + oy;
+            const int rx = nbs[0][nl] + ox;
+            const R wv = nw[ox][nl] * nw[4 + oy][nl] * nw[8 + oz][nl];
+            if (rz >= 0 && rz < ez) {  // outside only for wall layers (dropped)
+                const int c = (rz * ey + ry) * ex + rx;
+                rg[c] += nf[0][nl] * wv;
+                rg[MAXP + c] += nf[1][nl] * wv;
+                rg[2 * MAXP + c] += nf[2][nl] * wv;
+            }
         }
     }
     __syncthreads();
+    // block partial = region 0 + region 1 + ... (fixed order)
     IBLB_GLOBAL R *out = (IBLB_GLOBAL R *)P.part + (int64_t)blk * 3 * MAXP;
-    for (int c = lane; c < ncell; c += 64) {
-        out[c] = reg[c];
-        out[MAXP + c] = reg[MAXP + c];
-        out[2 * MAXP + c] = reg[2 * MAXP + c];
-    }
+    for (int c = tid; c < ncell; c += 256)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            R v = reg[0][k * MAXP + c];
+#pragma unroll
+            for (int r = 1; r < NR; ++r) v += reg[r][k * MAXP + c];
+            out[k * MAXP + c] = v;
+        }
 }
 
 // ----------------------------------------------------- stamped-tile list
@@ -317,7 +351,8 @@ __global__ void __launch_bounds__(256) k_compact(DevPtrs P) {
     const int slot = ctr & 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) P.tile_count[slot ^ 1] = 0;
     if (c >= P.total_tiles / TILE_CELLS) return;
-    const BoxDev &B = P.boxes[P.tchunk_box[c]];
+    const int box = P.tchunk_box[c];
+    const BoxDev &B = P.boxes[box];
     const int lt = c * TILE_CELLS + lane - B.tile_base;
     const bool st = lt < B.n_tiles && ((const IBLB_GLOBAL int32_t *)B.stamp)[lt] == ctr;
     const uint64_t m = __ballot(st);
@@ -325,7 +360,11 @@ __global__ void __launch_bounds__(256) k_compact(DevPtrs P) {
     int base = 0;
     if (lane == 0) base = atomicAdd(P.tile_count + slot, __popcll(m));
     base = __shfl(base, 0, 64);
-    if (st) P.tile_list[base + __popcll(m & ((1ull << lane) - 1ull))] = c * TILE_CELLS + lane;
+    if (st) {
+        const int k = base + __popcll(m & ((1ull << lane) - 1ull));
+        P.tile_list[2 * k] = c * TILE_CELLS + lane;
+        P.tile_list[2 * k + 1] = box;
+    }
 }
 
 // ---------------------------------------------------- interpolate + advect
@@ -342,8 +381,8 @@ __global__ void __launch_bounds__(256) k_interp(DevPtrs P, int mode, double *Uou
     __shared__ R red[3][3][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int blk = blockIdx.x;
-    const DropDev &D = P.drops[P.blk_drop[blk]];
-    const BoxDev &B = P.boxes[D.box];
+    const DropDev &D = P.drops[P.blk_drop[2 * blk]];
+    const BoxDev &B = P.boxes[P.blk_drop[2 * blk + 1]];
     const int N = P.Ntot, nb = P.nblk;
     const bool zper = B.zbc == 1;
     const IBLB_GLOBAL R *ub = (const IBLB_GLOBAL R *)B.uband;
@@ -586,8 +625,8 @@ hipError_t launch_set_v0(const DevPtrs &P, bool, hipStream_t s) {
 
 hipError_t launch_node(const DevPtrs &P, bool f64, int mode, hipStream_t s) {
     if (P.nblk == 0) return hipSuccess;
-    if (f64) hipLaunchKernelGGL(k_node<double>, dim3(P.nblk), dim3(64), 0, s, P, mode);
-    else hipLaunchKernelGGL(k_node<float>, dim3(P.nblk), dim3(64), 0, s, P, mode);
+    if (f64) hipLaunchKernelGGL(k_node<double>, dim3(P.nblk), dim3(256), 0, s, P, mode);
+    else hipLaunchKernelGGL(k_node<float>, dim3(P.nblk), dim3(256), 0, s, P, mode);
     if (mode == 0 && P.total_tiles > 0) {
         const int chunks = P.total_tiles / TILE_CELLS;
         hipLaunchKernelGGL(k_compact, dim3((chunks + 3) / 4), dim3(256), 0, s, P);
