@@ -192,16 +192,26 @@ iblb_status iblb_interpolate(struct iblb_ctx *ctx, int32_t d, const double *u_in
 iblb_status iblb_read_bins(struct iblb_ctx *ctx, int32_t d, int32_t *base_out);
 iblb_status iblb_read_csr(struct iblb_ctx *ctx, int32_t d, int32_t *offsets, int32_t *entries);
 
-/* Launch shape of the fused stream-collide kernel: threads along x per row
- * (a multiple of 32) and rows handled by one workgroup; their product must be
- * a multiple of 64 and at most 256.  streaming_stores (0 or 1) writes the
- * populations with non-temporal stores, which helps once the two population
- * buffers exceed the GPU's last-level cache and hurts while they fit.  Other
- * values return IBLB_E_INVAL.  Rebuilds the step graphs.  Synchronising. */
+/* Launch configuration of the fused stream-collide kernel:
+ *   threads_x         threads along x per row, a multiple of 32;
+ *   rows_per_group    rows of a workgroup; threads_x * rows_per_group must be
+ *                     a multiple of 64 and at most 256;
+ *   cells_per_thread  1 or 2 rows handled by a thread at a time (their loads
+ *                     issued together); 2 needs threads_x a multiple of 64;
+ *   streaming_stores  0 or 1: write the populations with non-temporal stores
+ *                     (helps once the two population buffers exceed the GPU's
+ *                     last-level cache, hurts while they fit);
+ *   max_workgroups    0, or a cap on the grid: the workgroups then loop over
+ *                     the rows, leaving compute units to the mesh kernels that
+ *                     run beside the stream-collide.
+ * Other values return IBLB_E_INVAL.  Rebuilds the step graphs.  Synchronising.
+ * Results do not depend on the configuration. */
 iblb_status iblb_set_launch(struct iblb_ctx *ctx, int32_t threads_x, int32_t rows_per_group,
-                            int32_t streaming_stores);
-iblb_status iblb_get_launch(const struct iblb_ctx *ctx, int32_t *threads_x,
-                            int32_t *rows_per_group, int32_t *streaming_stores);
+                            int32_t cells_per_thread, int32_t streaming_stores,
+                            int32_t max_workgroups);
+iblb_status iblb_get_launch(const struct iblb_ctx *ctx, int32_t *threads_x, int32_t *rows_per_group,
+                            int32_t *cells_per_thread, int32_t *streaming_stores,
+                            int32_t *max_workgroups);
 
 /* Average device time (ms) of one stream-collide launch over `reps` launches,
  * measured with HIP events on the context's stream (the populations are

@@ -91,8 +91,8 @@ def load():
     L.iblb_interpolate.argtypes = [vp, i32, dp, dp]
     L.iblb_read_bins.argtypes = [vp, i32, ip]
     L.iblb_read_csr.argtypes = [vp, i32, ip, ip]
-    L.iblb_set_launch.argtypes = [vp, i32, i32, i32]
-    L.iblb_get_launch.argtypes = [vp, ip, ip, ip]
+    L.iblb_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
+    L.iblb_get_launch.argtypes = [vp, ip, ip, ip, ip, ip]
     L.iblb_time_stream_collide.argtypes = [vp, i32, dp]
     L.iblb_destroy.argtypes = [vp]
     L.iblb_last_error.argtypes = [vp]
@@ -269,14 +269,16 @@ class Simulation:
         self._chk(load().iblb_read_csr(self.ctx, d, _iptr(off), _iptr(ent)))
         return off, ent
 
-    def set_launch(self, threads_x, rows, streaming_stores=0):
-        self._chk(load().iblb_set_launch(self.ctx, int(threads_x), int(rows), int(streaming_stores)))
+    def set_launch(self, threads_x, rows, cells_per_thread=1, streaming_stores=0, max_workgroups=0):
+        self._chk(load().iblb_set_launch(self.ctx, int(threads_x), int(rows), int(cells_per_thread),
+                                         int(streaming_stores), int(max_workgroups)))
 
     def get_launch(self):
-        """(threads_x, rows_per_group, streaming_stores) of the bulk kernel."""
-        a, b, n = C.c_int32(), C.c_int32(), C.c_int32()
-        self._chk(load().iblb_get_launch(self.ctx, C.byref(a), C.byref(b), C.byref(n)))
-        return a.value, b.value, n.value
+        """(threads_x, rows_per_group, cells_per_thread, streaming_stores,
+        max_workgroups) of the bulk kernel."""
+        v = [C.c_int32() for _ in range(5)]
+        self._chk(load().iblb_get_launch(self.ctx, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def time_stream_collide(self, reps=10):
         ms = C.c_double()

@@ -333,7 +333,6 @@ struct iblb_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     DevPtrs P{};
     Launch L{};
-    int rows_per_group = 1;
     hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][advect first]
     bool pending = false;  // advection of the last step not yet applied
     int parity = 0;
@@ -344,6 +343,7 @@ struct iblb_ctx {
     std::string err = "no error";
     double *host_obs = nullptr;
     uint32_t *host_status = nullptr;
+    std::vector<char> init_qh, init_ql;  // initial node positions, kept during init only
 };
 
 namespace {
@@ -365,13 +365,14 @@ bool is_f64(const iblb_ctx *c) { return c->plan.storage == IBLB_F64; }
 
 iblb_status upload_rows(iblb_ctx *c) {
     std::vector<RowGroup> rows;
-    const int R = c->rows_per_group;
+    const int R = c->L.by * c->L.cpt;
     for (int b = 0; b < (int)c->plan.boxes.size(); ++b) {
         const int nr = c->plan.boxes[b].b.ny * c->plan.boxes[b].b.nz;
         for (int r = 0; r < nr; r += R) rows.push_back({b, r, std::min(r + R, nr), 0});
     }
     c->P.n_rowgroups = (int)rows.size();
     c->L.grid = (int)rows.size();
+    if (c->L.maxg > 0 && c->L.maxg < c->L.grid) c->L.grid = c->L.maxg;
     HIPCHK(c, hipMemcpyAsync(c->P.rows, rows.data(), rows.size() * sizeof(RowGroup),
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -449,13 +450,17 @@ iblb_status build_graphs(iblb_ctx *c) {
     return IBLB_OK;
 }
 
-iblb_status check_launch(iblb_ctx *c, int bx, int by) {
-    if (bx < 32 || (bx & 31) || by < 1 || bx * by > K1_MAX_THREADS || (bx * by) % 64)
-        return set_err(c, IBLB_E_INVAL, "launch shape: threads_x a multiple of 32, "
-                                        "threads_x*rows a multiple of 64 and <= " +
-                                            std::to_string(K1_MAX_THREADS));
-    return IBLB_OK;
+// Why a bulk launch configuration is not valid (nullptr if it is).
+const char *launch_problem(const Launch &L) {
+    if (L.bx < 32 || (L.bx & 31) || L.by < 1 || L.bx * L.by > K1_MAX_THREADS || (L.bx * L.by) % 64)
+        return "launch shape: threads_x a multiple of 32, threads_x*rows a multiple of 64 and <= 256";
+    if (L.cpt != 1 && L.cpt != 2) return "cells_per_thread must be 1 or 2";
+    if (L.cpt == 2 && L.bx % 64) return "cells_per_thread 2 needs threads_x a multiple of 64";
+    if (L.nt != 0 && L.nt != 1) return "streaming_stores must be 0 or 1";
+    if (L.maxg < 0) return "max_workgroups must be >= 0";
+    return nullptr;
 }
+static_assert(K1_MAX_THREADS == 256, "launch_problem() states the bound");
 
 iblb_status time_k1(iblb_ctx *c, int reps, double *ms) {
     hipEvent_t a, b;
@@ -477,43 +482,127 @@ iblb_status time_k1(iblb_ctx *c, int reps, double *ms) {
     return IBLB_OK;
 }
 
+// Back to the state iblb_init leaves: fluid at rest, initial node positions,
+// no pending advection, step 0 (the device epoch keeps counting).
+iblb_status reset_state(iblb_ctx *c) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &H : c->plan.boxes)
+        for (int k = 0; k < 2; ++k)
+            HIPCHK(c, hipMemsetAsync(c->ws + H.off_f[k], 0,
+                                     (size_t)Q * H.plane * elem_bytes(c->plan.storage), c->stream));
+    if (!c->init_qh.empty()) {
+        HIPCHK(c, hipMemcpyAsync(c->P.qh, c->init_qh.data(), c->init_qh.size(), hipMemcpyHostToDevice,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->P.ql, c->init_ql.data(), c->init_ql.size(), hipMemcpyHostToDevice,
+                                 c->stream));
+    }
+    HIPCHK(c, hipMemsetAsync(c->P.status, 0, 4, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->pending) {
+        // the dropped advection would have started a new epoch: start it here,
+        // so that the next stamping pass does not meet the last one's stamps
+        HIPCHK(c, launch_epoch(c->P, c->stream));
+        ++c->epoch;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->pending = false;
+    c->parity = 0;
+    c->step = 0;
+    c->last_step_epoch = -1;
+    c->unstable = false;
+    return IBLB_OK;
+}
+
+// Mean device time (ms) of one graph-replayed step, best of three runs.
+iblb_status time_steps(iblb_ctx *c, double *ms) {
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    iblb_status st = iblb_step(c, 20);
+    *ms = 1e300;
+    for (int rep = 0; rep < 3 && st == IBLB_OK; ++rep) {
+        HIPCHK(c, hipEventRecord(a, c->stream));
+        st = iblb_step(c, 40);
+        HIPCHK(c, hipEventRecord(b, c->stream));
+        HIPCHK(c, hipEventSynchronize(b));
+        float t = 0;
+        HIPCHK(c, hipEventElapsedTime(&t, a, b));
+        *ms = std::min(*ms, (double)t / 40);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return st;
+}
+
 iblb_status autotune(iblb_ctx *c) {
     int nxmax = 0;
     for (auto &H : c->plan.boxes) nxmax = std::max(nxmax, H.b.nx);
     const int saved_parity = c->parity;
-    double best = 1e300;
-    int bbx = c->L.bx, bby = c->L.by, bnt = c->L.nt;
+    auto timed = [&](const Launch &L, double *ms) -> iblb_status {
+        c->L = L;
+        iblb_status st = upload_rows(c);
+        if (st != IBLB_OK) return st;
+        double t = 0;
+        *ms = 1e300;
+        st = time_k1(c, 3, &t);
+        for (int rep = 0; rep < 3 && st == IBLB_OK; ++rep) {
+            st = time_k1(c, 10, &t);
+            *ms = std::min(*ms, t);
+        }
+        return st;
+    };
+    // 1. block shape, rows per thread, store policy: fastest bulk kernel
+    Launch best = c->L;
+    double tbest = 1e300;
     for (int nt : {0, 1})
-    for (int bx : {32, 64, 128, 256}) {
-        if (bx > (int)round_up((size_t)nxmax, 32)) continue;
-        for (int threads : {64, 128, K1_MAX_THREADS}) {
-            const int by = threads / bx;
-            if (by < 1 || check_launch(c, bx, by) != IBLB_OK) continue;
-            c->L.bx = bx;
-            c->L.by = by;
-            c->L.nt = nt;
-            c->rows_per_group = by;
+        for (int bx : {32, 64, 128, 256}) {
+            if (bx > (int)round_up((size_t)nxmax, 32)) continue;
+            for (int threads : {64, 128, K1_MAX_THREADS})
+                for (int cpt : {1, 2}) {
+                    const Launch L{bx, threads / bx, 0, nt, cpt, 0};
+                    if (L.by < 1 || launch_problem(L)) continue;
+                    double ms = 0;
+                    iblb_status st = timed(L, &ms);
+                    if (st != IBLB_OK) return st;
+                    if (ms < tbest) {
+                        tbest = ms;
+                        best = L;
+                    }
+                }
+        }
+    // 2. with meshes present and the step replayed as graphs, a cap on the
+    //    bulk grid is judged by whole steps: the workgroups it does not take
+    //    leave CU slots to the mesh kernels that run beside it, at some cost
+    //    in bulk bandwidth.  Each candidate starts from the initial state.
+    if (c->plan.nblk > 0 && (c->plan.flags & IBLB_FLAG_GRAPH)) {
+        int dev = 0, cus = 0;
+        HIPCHK(c, hipGetDevice(&dev));
+        HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int wpg = best.bx * best.by / 64;  // waves per workgroup
+        double sbest = 1e300;
+        Launch chosen = best;
+        for (int waves_per_cu : {0, 16, 12, 8, 6}) {
+            Launch L = best;
+            L.maxg = waves_per_cu ? std::max(1, cus * waves_per_cu / wpg) : 0;
+            c->L = L;
             iblb_status st = upload_rows(c);
             if (st != IBLB_OK) return st;
-            double ms = 1e300, t = 0;
-            st = time_k1(c, 3, &t);
-            for (int rep = 0; rep < 3 && st == IBLB_OK; ++rep) {
-                st = time_k1(c, 10, &t);
-                ms = std::min(ms, t);
-            }
+            if (L.maxg && c->L.grid >= c->P.n_rowgroups) continue;  // no cap at this size
+            double ms = 0;
+            st = reset_state(c);
+            if (st == IBLB_OK) st = build_graphs(c);
+            if (st == IBLB_OK) st = time_steps(c, &ms);
             if (st != IBLB_OK) return st;
-            if (ms < best) {
-                best = ms;
-                bbx = bx;
-                bby = by;
-                bnt = nt;
+            if (ms < sbest) {
+                sbest = ms;
+                chosen = L;
             }
         }
+        best = chosen;
+        iblb_status st = reset_state(c);
+        if (st != IBLB_OK) return st;
     }
-    c->L.bx = bbx;
-    c->L.by = bby;
-    c->L.nt = bnt;
-    c->rows_per_group = bby;
+    c->L = best;
     iblb_status st = upload_rows(c);
     if (st != IBLB_OK) return st;
     // the timing runs advanced the fluid without the meshes: back to rest
@@ -758,6 +847,10 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     HIPCHK(c, hipMemcpyAsync(P.drops, dd.data(), dd.size() * sizeof(DropDev), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(P.qh, qh.data(), qh.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(P.ql, ql.data(), ql.size(), hipMemcpyHostToDevice, c->stream));
+    if (p.flags & IBLB_FLAG_AUTOTUNE) {
+        c->init_qh = qh;
+        c->init_ql = ql;
+    }
     HIPCHK(c, hipMemcpyAsync(P.tri, tri.data(), 3 * (size_t)p.Ttot * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(P.csr_off, csr_off.data(), csr_off.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(P.csr_ent, csr_ent.data(), 3 * (size_t)p.Ttot * 4, hipMemcpyHostToDevice, c->stream));
@@ -793,9 +886,12 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     size_t pop_bytes = 0;
     for (auto &H : p.boxes) pop_bytes += 2 * (size_t)Q * H.plane * elem_bytes(p.storage);
     c->L.nt = pop_bytes > ((size_t)256 << 20) ? 1 : 0;
-    c->rows_per_group = c->L.by;
+    c->L.cpt = 1;
+    c->L.maxg = 0;
     st = upload_rows(c);
     if (st == IBLB_OK && (p.flags & IBLB_FLAG_AUTOTUNE)) st = autotune(c);
+    c->init_qh = std::vector<char>();
+    c->init_ql = std::vector<char>();
     if (st == IBLB_OK) st = build_graphs(c);
     if (st == IBLB_OK) {
         if (hipHostMalloc((void **)&c->host_obs,
@@ -1202,26 +1298,25 @@ iblb_status iblb_read_csr(iblb_ctx *c, int32_t d, int32_t *offsets, int32_t *ent
     return IBLB_OK;
 }
 
-iblb_status iblb_set_launch(iblb_ctx *c, int32_t bx, int32_t by, int32_t nt) {
+iblb_status iblb_set_launch(iblb_ctx *c, int32_t bx, int32_t by, int32_t cpt, int32_t nt, int32_t maxg) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
-    iblb_status st = check_launch(c, bx, by);
-    if (st != IBLB_OK) return st;
-    if (nt != 0 && nt != 1) return set_err(c, IBLB_E_INVAL, "streaming_stores must be 0 or 1");
+    const Launch L{bx, by, 0, nt, cpt, maxg};
+    if (const char *why = launch_problem(L)) return set_err(c, IBLB_E_INVAL, why);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->L.bx = bx;
-    c->L.by = by;
-    c->L.nt = nt;
-    c->rows_per_group = by;
-    st = upload_rows(c);
+    c->L = L;
+    iblb_status st = upload_rows(c);
     if (st == IBLB_OK) st = build_graphs(c);
     return st;
 }
 
-iblb_status iblb_get_launch(const iblb_ctx *c, int32_t *bx, int32_t *by, int32_t *nt) {
-    if (!c || !bx || !by || !nt) return set_err(nullptr, IBLB_E_INVAL, "NULL argument");
+iblb_status iblb_get_launch(const iblb_ctx *c, int32_t *bx, int32_t *by, int32_t *cpt, int32_t *nt,
+                            int32_t *maxg) {
+    if (!c || !bx || !by || !cpt || !nt || !maxg) return set_err(nullptr, IBLB_E_INVAL, "NULL argument");
     *bx = c->L.bx;
     *by = c->L.by;
+    *cpt = c->L.cpt;
     *nt = c->L.nt;
+    *maxg = c->L.maxg;
     return IBLB_OK;
 }
 

@@ -16,7 +16,7 @@ namespace iblb {
 // streaming stores (they are read again only in the next step; pays off
 // once the two population buffers exceed the last-level cache).  Cells
 // next to a mesh are recomputed by the band kernel afterwards.
-template <int ST, bool UROW, bool NT>
+template <int ST, bool UROW, bool NT, int CPT>
 __global__ void __launch_bounds__(K1_MAX_THREADS)
     k_bulk(DevPtrs P, int parity, int full_u, float scale, float inv) {
     using S = Stor<ST>;
@@ -41,39 +41,56 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
         IBLB_GLOBAL R *__restrict__ uf = (IBLB_GLOBAL R *)B->ufull;
         const uint64_t plane = (uint64_t)B->plane;
         const PopRes rs = pop_res((const void *)src, pb), rd = pop_res((const void *)dst, pb);
-        // row r = z * ny + y, stepped by BY without a division per row
+        // row r = z * ny + y, stepped by BY without a division per row; a
+        // thread takes CPT rows (BY apart) at a time, with the loads of all
+        // of them issued before the first collision
         int r = rg.r0 + ty;
         int z = r / ny, y = r - z * ny;
-        for (; r < rg.r1; r += BY) {
-            const int ry = UROW ? __builtin_amdgcn_readfirstlane(y) : y;
-            const int rz = UROW ? __builtin_amdgcn_readfirstlane(z) : z;
-            const RowAddr ra = row_addr(ry, rz, ny, nz, sx, zper, EB);
-            for (int x = tx; x < nx; x += BX) {
-                R g[Q], out[Q], u[3], rho;
-                const XOff xo = x_off<EB>(x, nx);
-                const uint32_t own = ra.ro[1][1] + xo.c;
-                if constexpr (BUF)
-                    pull_buf<ST>(rs, (uint32_t)pb, ra, xo, g);
-                else
-                    pull_raw<ST>(src, pb, ra, xo, g);
-                collide<ST>(g, gx, gy, gz, rho0, omega, guo, scale, inv, out, u, rho);
-                if constexpr (BUF)
-                    store_buf<ST, NT>(rd, (uint32_t)pb, ra.ro[1][1], xo.c, out);
-                else
-                    store_ptr<ST, NT>(dst, pb, own, out);
-                if (full_u) {
-                    const uint64_t e = own / EB;
-                    uf[e] = u[0];
-                    uf[plane + e] = u[1];
-                    uf[2 * plane + e] = u[2];
+        for (; r < rg.r1; r += BY * CPT) {
+            RowAddr ra[CPT];
+            bool on[CPT];
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                on[k] = r + k * BY < rg.r1;
+                const int ry = UROW ? __builtin_amdgcn_readfirstlane(y) : y;
+                const int rz = UROW ? __builtin_amdgcn_readfirstlane(z) : z;
+                ra[k] = row_addr(ry, rz, ny, nz, sx, zper, EB);
+                y += BY;
+                while (y >= ny) {
+                    y -= ny;
+                    ++z;
                 }
-                if (!(rho > R(0) && rho < R(FLT_MAX))) atomicOr(P.status, BIT_RHO);
-                if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > R(1) / R(3)) atomicOr(P.status, BIT_MACH);
             }
-            y += BY;
-            while (y >= ny) {
-                y -= ny;
-                ++z;
+            for (int x = tx; x < nx; x += BX) {
+                R g[CPT][Q];
+                const XOff xo = x_off<EB>(x, nx);
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    if (!on[k]) continue;
+                    if constexpr (BUF)
+                        pull_buf<ST>(rs, (uint32_t)pb, ra[k], xo, g[k]);
+                    else
+                        pull_raw<ST>(src, pb, ra[k], xo, g[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    if (!on[k]) continue;
+                    R out[Q], u[3], rho;
+                    const uint32_t own = ra[k].ro[1][1] + xo.c;
+                    collide<ST>(g[k], gx, gy, gz, rho0, omega, guo, scale, inv, out, u, rho);
+                    if constexpr (BUF)
+                        store_buf<ST, NT>(rd, (uint32_t)pb, ra[k].ro[1][1], xo.c, out);
+                    else
+                        store_ptr<ST, NT>(dst, pb, own, out);
+                    if (full_u) {
+                        const uint64_t e = own / EB;
+                        uf[e] = u[0];
+                        uf[plane + e] = u[1];
+                        uf[2 * plane + e] = u[2];
+                    }
+                    if (!(rho > R(0) && rho < R(FLT_MAX))) atomicOr(P.status, BIT_RHO);
+                    if (u[0] * u[0] + u[1] * u[1] + u[2] * u[2] > R(1) / R(3)) atomicOr(P.status, BIT_MACH);
+                }
             }
         }
     }
@@ -229,7 +246,7 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
     const int nwaves = gridDim.x * 4;
     // the epoch counter and both list lengths in one round trip
     const int ctr = *P.ctr, n0 = P.tile_count[0], n1 = P.tile_count[1];
-    const int count = (ctr & 1) ? n1 : n0;
+    const int count = min((ctr & 1) ? n1 : n0, P.total_tiles);
     const IBLB_CONST int32_t *tl = (const IBLB_CONST int32_t *)P.tile_list;
     for (int i = wave; i < count; i += nwaves) {
         const int gt = tl[2 * i];  // global tile id and its box
@@ -367,23 +384,33 @@ __global__ void __launch_bounds__(256) k_box_obs_final(DevPtrs P, int box, int g
 }
 
 // ---------------------------------------------------------------- launchers
+template <int ST, bool UROW, bool NT>
+static void launch_bulk_c(const DevPtrs &P, int parity, int full_u, float scale, float inv, const Launch &L,
+                          dim3 grid, dim3 block, hipStream_t s) {
+    if (UROW && L.cpt == 2)
+        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    else
+        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1>), grid, block, 0, s, P, parity, full_u, scale, inv);
+}
+
 template <int ST>
 static hipError_t launch_bulk_t(const DevPtrs &P, int parity, int full_u, float scale, const Launch &L,
                                 hipStream_t s) {
     // never launch a shape the kernel was not compiled for
-    if (L.bx < 1 || L.by < 1 || L.bx * L.by > K1_MAX_THREADS || L.grid < 1) return hipErrorInvalidValue;
+    if (L.bx < 1 || L.by < 1 || L.bx * L.by > K1_MAX_THREADS || L.grid < 1 || L.cpt < 1 || L.cpt > 2)
+        return hipErrorInvalidValue;
     const dim3 block(L.bx, L.by), grid(L.grid);
     const float inv = 1.0f / scale;
     if (L.bx % 64 == 0) {
         if (L.nt)
-            hipLaunchKernelGGL((k_bulk<ST, true, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
+            launch_bulk_c<ST, true, true>(P, parity, full_u, scale, inv, L, grid, block, s);
         else
-            hipLaunchKernelGGL((k_bulk<ST, true, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+            launch_bulk_c<ST, true, false>(P, parity, full_u, scale, inv, L, grid, block, s);
     } else {
         if (L.nt)
-            hipLaunchKernelGGL((k_bulk<ST, false, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
+            launch_bulk_c<ST, false, true>(P, parity, full_u, scale, inv, L, grid, block, s);
         else
-            hipLaunchKernelGGL((k_bulk<ST, false, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+            launch_bulk_c<ST, false, false>(P, parity, full_u, scale, inv, L, grid, block, s);
     }
     return hipGetLastError();
 }

@@ -126,6 +126,8 @@ struct Launch {
     int bx, by;                 // bulk stream-collide block shape
     int grid;                   // bulk stream-collide grid (<= n_rowgroups)
     int nt;                     // bulk stream-collide writes with streaming stores
+    int cpt;                    // rows per thread and row group pass (1 or 2; 2 needs bx % 64 == 0)
+    int maxg;                   // cap on the grid (0: one workgroup per row group)
 };
 
 hipError_t launch_tri(const DevPtrs &P, bool f64, hipStream_t s);

@@ -360,8 +360,8 @@ __global__ void __launch_bounds__(256) k_compact(DevPtrs P) {
     int base = 0;
     if (lane == 0) base = atomicAdd(P.tile_count + slot, __popcll(m));
     base = __shfl(base, 0, 64);
-    if (st) {
-        const int k = base + __popcll(m & ((1ull << lane) - 1ull));
+    const int k = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (st && k < P.total_tiles) {  // one entry per tile and epoch: k < total_tiles always
         P.tile_list[2 * k] = c * TILE_CELLS + lane;
         P.tile_list[2 * k + 1] = box;
     }

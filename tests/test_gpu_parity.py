@@ -266,6 +266,27 @@ def test_runs_are_deterministic():
     assert np.array_equal(a.read_nodes(0), b.read_nodes(0))
 
 
+@pytest.mark.parametrize("storage", [F32, F16])
+def test_bulk_launch_configurations_give_identical_results(storage):
+    # shape, rows per thread, store policy and grid cap change only the
+    # schedule: every cell is computed by the same arithmetic
+    say("bulk launch configurations", storage)
+    wl = configs.plain_c1()
+    ref = None
+    for launch in ((32, 2, 1, 0, 0), (64, 1, 2, 0, 0), (64, 4, 2, 1, 0), (64, 2, 1, 1, 5),
+                   (64, 1, 2, 0, 3), (256, 1, 2, 1, 1)):
+        s = sim(wl, storage, flags=GRAPH)
+        s.set_launch(*launch)
+        s.step(30)
+        got = (s.read_state(0), s.read_nodes(0))
+        s.close()
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got[0], ref[0]), launch
+            assert np.array_equal(got[1], ref[1]), launch
+
+
 def _small_batch(seed=4):
     rng = np.random.default_rng(seed)
     boxes, drops = [], []
@@ -329,13 +350,14 @@ def test_set_launch_rejects_shapes_beyond_the_kernel_bound():
         with pytest.raises(P.IblbError) as e:
             s.set_launch(bx, by)
         assert e.value.code == -1
-    with pytest.raises(P.IblbError) as e:
-        s.set_launch(64, 4, 2)
-    assert e.value.code == -1
+    for bad in ((64, 4, 3, 0, 0), (32, 2, 2, 0, 0), (64, 4, 1, 2, 0), (64, 4, 1, 0, -1)):
+        with pytest.raises(P.IblbError) as e:
+            s.set_launch(*bad)
+        assert e.value.code == -1
     s.set_launch(64, 4)
-    assert s.get_launch() == (64, 4, 0)
-    s.set_launch(64, 4, 1)
-    assert s.get_launch() == (64, 4, 1)
+    assert s.get_launch() == (64, 4, 1, 0, 0)
+    s.set_launch(64, 4, 2, 1, 7)
+    assert s.get_launch() == (64, 4, 2, 1, 7)
     s.step(3)
 
 
