@@ -10,6 +10,10 @@ besides the headline it carries:
     trace of the same run (tests/golden/spreading_trace_oracle.json);
   - the same run with FP16- and BF16-deviation storage (speed and error);
   - the bulk stream-collide kernel on an HBM-resident 256x256x128 box;
+  - the 256x256x128 precision workload (40,962-node droplet, tau 0.6 and
+    1.0) in FP64, FP32, FP16- and BF16-deviation storage, with observable
+    errors against the stored FP64 oracle trace and against the FP64 run;
+  - the 512x512x256 box with 16 droplets in FP32 and FP16-deviation storage;
   - the 64-box batched workload in one context against 64 sequential runs;
   - the FP64 oracle timed on the host cores (cpu_baseline).
 """
@@ -32,6 +36,8 @@ STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
 ELEM = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
 BYTES_PER_NODE = 150.0  # per IB node and step: q, phi, weights, CSR, triangle records
 TRACE = os.path.join(ROOT, "tests", "golden", "spreading_trace_oracle.json")
+PTRACE = os.path.join(ROOT, "tests", "golden", "precision_trace_oracle_tau{tau:g}.json")
+OBS = ("height", "contact_radius", "volume", "area")
 TRAFFIC = os.path.join(ROOT, "profiles", "bulk_collide_traffic.json")
 
 
@@ -54,6 +60,17 @@ def make_sim(wl, storage, autotune=True):
     flags = P.IBLB_FLAG_GRAPH | (P.IBLB_FLAG_AUTOTUNE if autotune else 0)
     return P.Simulation(wl, storage=STORAGE[storage], flags=flags,
                         dev_scale=4096.0 if storage == "f16dev" else 1.0)
+
+
+def rel_errors(got, ref, keys=OBS):
+    return {k: abs(got[k] - ref[k]) / abs(ref[k]) for k in keys}
+
+
+def bulk_rate(sim, cells, storage, reps=50):
+    """Bulk kernel alone, in the context's launch configuration: (ms, GB/s)."""
+    sim.time_stream_collide(reps=3)
+    ms = sim.time_stream_collide(reps=reps)
+    return ms, cells * cell_bytes(storage) / (ms * 1e-3) / 1e9
 
 
 def timed_steps(sim, steps):
@@ -151,6 +168,60 @@ def variants(args, f32_drop, total_steps):
                                 "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                                 "launch": list(sim.get_launch())}
         sim.close()
+    # precision workload: FP64 / FP32 / FP16 / BF16 storage on the same run
+    for tau in (0.6, 1.0):
+        wl = configs.precision_c3(tau=tau, steps=args.precision_steps)
+        ref_path = PTRACE.format(tau=tau)
+        oracle_row = None
+        if os.path.exists(ref_path):
+            with open(ref_path) as fh:
+                tr = json.load(fh)
+            oracle_row = {r["step"]: r for r in tr["rows"]}.get(args.precision_steps)
+        runs = {}
+        for st in ("f64", "f32", "f16dev", "bf16dev"):
+            sim = make_sim(wl, st)
+            sim.step(20)
+            dt = timed_steps(sim, args.precision_steps - 20)
+            d, b = sim.observables()
+            ms, gbs = bulk_rate(sim, wl.cells, st)
+            obs = {k: d[0][k] for k in OBS}
+            obs["mass"] = b[0]["mass"]
+            runs[st] = {"mlups": round(wl.cells * (args.precision_steps - 20) / dt / 1e6, 1),
+                        "ms_per_step": dt / (args.precision_steps - 20) * 1e3,
+                        "bulk_GBs": round(gbs, 1), "bulk_frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "launch": list(sim.get_launch()), "obs": obs}
+            sim.close()
+        for st, r in runs.items():
+            r["rel_err_vs_f64_gpu"] = rel_errors(r["obs"], runs["f64"]["obs"], OBS + ("mass",))
+            if oracle_row is not None:
+                r["rel_err_vs_oracle"] = rel_errors(r["obs"], oracle_row, OBS + ("mass",))
+            r["speedup_vs_f32"] = runs["f32"]["ms_per_step"] / r["ms_per_step"]
+        out[f"precision_tau{tau:g}"] = {"workload": wl.name, "steps": args.precision_steps,
+                                         "oracle_trace": oracle_row is not None, "runs": runs}
+    # the 512x512x256 box with 16 droplets: FP32 against FP16-deviation storage
+    if not args.no_large:
+        wl = configs.multidroplet_c5()
+        runs = {}
+        for st in ("f32", "f16dev"):
+            sim = make_sim(wl, st)
+            sim.step(20)
+            dt = timed_steps(sim, args.large_steps)
+            drops, boxes = sim.observables()
+            ms, gbs = bulk_rate(sim, wl.cells, st, reps=20)
+            runs[st] = {"mlups": round(wl.cells * args.large_steps / dt / 1e6, 1),
+                        "ib_nodes_per_s": wl.nodes * args.large_steps / dt,
+                        "ms_per_step": dt / args.large_steps * 1e3, "bulk_GBs": round(gbs, 1),
+                        "bulk_frac": round(gbs / HBM_PEAK_GBS, 4), "launch": list(sim.get_launch()),
+                        "drops": [{k: d[k] for k in OBS} for d in drops], "mass": boxes[0]["mass"]}
+            sim.close()
+        worst = {k: max(abs(a[k] - b[k]) / abs(b[k]) for a, b in zip(runs["f16dev"]["drops"], runs["f32"]["drops"]))
+                 for k in OBS}
+        for r in runs.values():
+            r.pop("drops")
+        out["large_multidroplet"] = {"workload": wl.name, "cells": wl.cells, "ib_nodes": wl.nodes,
+                                     "steps": args.large_steps, "runs": runs,
+                                     "f16dev_worst_rel_err_vs_f32": worst,
+                                     "f16dev_speedup_vs_f32": runs["f32"]["ms_per_step"] / runs["f16dev"]["ms_per_step"]}
     # batched: 64 uneven boxes in one context vs 64 sequential contexts
     if not args.no_batched:
         wl = configs.batched_c4()
@@ -182,7 +253,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGE))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--batched-steps", type=int, default=1000)
+    ap.add_argument("--precision-steps", type=int, default=2000)
+    ap.add_argument("--large-steps", type=int, default=500)
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -205,6 +279,10 @@ def main():
     bytes_k1 = cells * cell_bytes(args.storage)
     achieved = bytes_k1 / (k1_ms * 1e-3) / 1e9
     launch = sim.get_launch()
+    # the same kernel without the grid cap the step uses to leave CU slots to
+    # the concurrent mesh kernels
+    sim.set_launch(*launch[:4], 0)
+    k1_free_ms = sim.time_stream_collide(reps=200)
     sim.close()
     tr = traffic_record()
     traffic = None
@@ -225,7 +303,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_bulk (fused pull-stream/collide, every cell)",
-                     "kernel_ms": k1_ms, "bytes_per_launch": bytes_k1, "band_cells": band},
+                     "kernel_ms": k1_ms, "bytes_per_launch": bytes_k1, "band_cells": band,
+                     "launch": list(launch),
+                     "uncapped": {"kernel_ms": k1_free_ms,
+                                  "achieved": round(bytes_k1 / (k1_free_ms * 1e-3) / 1e9, 1),
+                                  "frac": round(bytes_k1 / (k1_free_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
         "observables": {"step": drop["step"], "height": drop["height"],
                         "contact_radius": drop["contact_radius"], "volume": drop["volume"],
                         "mass": box["mass"]},

@@ -20,7 +20,7 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--storage", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--launch-spreading", type=int, nargs=5, default=(128, 1, 1, 0, 0),
+    ap.add_argument("--launch-spreading", type=int, nargs=5, default=(128, 1, 1, 0, 1024),
                     help="threads_x rows cells_per_thread streaming_stores max_workgroups of the "
                          "bulk launch on the spreading workload")
     ap.add_argument("--launch-box", type=int, nargs=5, default=(256, 1, 1, 1, 0),
