@@ -175,8 +175,8 @@ iblb_status iblb_write_nodes(struct iblb_ctx *ctx, int32_t d, const double *node
  *   compute_forces : nodal forces phi_j (Eqs. 9-11), [n_nodes][3]
  *   compute_spread : spread force density F (Eq. 8) of box b,
  *                    [3][nz][ny][nx], zero away from the meshes; and the
- *                    flags of the 4x4x4 tiles holding a stencil cell,
- *                    [ceil(nz/4)][ceil(ny/4)][ceil(nx/4)] (may be NULL)
+ *                    flags of the band tiles holding a stencil cell (tile
+ *                    shape and numbering: iblb_band_tile; may be NULL)
  *   interpolate    : U_j = sum_x u(x) Delta(q_j - x) (Eq. 7) of a given
  *                    [3][nz][ny][nx] field u, without moving the nodes
  *   read_bins      : base cell floor(q - 1/2) per axis, x and y wrapped
@@ -212,6 +212,12 @@ iblb_status iblb_set_launch(struct iblb_ctx *ctx, int32_t threads_x, int32_t row
 iblb_status iblb_get_launch(const struct iblb_ctx *ctx, int32_t *threads_x, int32_t *rows_per_group,
                             int32_t *cells_per_thread, int32_t *streaming_stores,
                             int32_t *max_workgroups);
+
+/* Shape of the band tiles that iblb_compute_spread's tile_flags refer to:
+ * shape[0..2] = cells per tile along x, y, z (a tile is 64 cells).  Tiles are
+ * numbered x fastest: ((tz * tiles_y) + ty) * tiles_x + tx, tiles_a =
+ * ceil(n_a / shape[a]).  Host memory; no device. */
+iblb_status iblb_band_tile(int32_t *shape);
 
 /* Average device time (ms) of one stream-collide launch over `reps` launches,
  * measured with HIP events on the context's stream (the populations are

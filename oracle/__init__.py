@@ -78,7 +78,7 @@ def _declare(L):
     L.orc_node_forces.restype = _i
     L.orc_csr.argtypes = [_i, _i, _ip, _ip, _ip]
     L.orc_base_cells.argtypes = [_i, _dp, _i, _i, _ip]
-    L.orc_touched_tiles.argtypes = [_i, _dp, _i, _i, _i, _i, _i, _bp]
+    L.orc_touched_tiles.argtypes = [_i, _dp, _i, _i, _i, _i, _i, _i, _i, _bp]
     L.orc_mesh_observables.argtypes = [_i, _i, _ip, _dp, _d, _dp]
 
 
@@ -229,11 +229,14 @@ def base_cells(q, nx, ny):
     return b
 
 
-def touched_tiles(q, shape, zbc, tile=4):
+def touched_tiles(q, shape, zbc, tile=(4, 4, 4)):
+    """Flags [tiles_z][tiles_y][tiles_x] of the tiles (tile = cells per tile
+    along x, y, z) that hold a cell of some node's 4x4x4 stencil."""
     nz, ny, nx = shape
-    tn = [(n + tile - 1) // tile for n in (nz, ny, nx)]
+    tx, ty, tz = tile
+    tn = [(nz + tz - 1) // tz, (ny + ty - 1) // ty, (nx + tx - 1) // tx]
     flags = _np.zeros(tn, _np.uint8)
-    lib().orc_touched_tiles(len(q), _f64(q), nx, ny, nz, int(zbc), tile, flags)
+    lib().orc_touched_tiles(len(q), _f64(q), nx, ny, nz, int(zbc), tx, ty, tz, flags)
     return flags
 
 

@@ -480,9 +480,9 @@ void orc_base_cells(int N, const double *q, int nx, int ny, int32_t *base) {
  * (tz*ty_n + ty)*tx_n + tx) that holds a stencil cell of any node; stencil
  * cells outside [0, nz) in z are skipped when the box has walls.
  */
-void orc_touched_tiles(int N, const double *q, int nx, int ny, int nz, int zbc, int tile,
-                       uint8_t *flags) {
-    int tnx = (nx + tile - 1) / tile, tny = (ny + tile - 1) / tile;
+void orc_touched_tiles(int N, const double *q, int nx, int ny, int nz, int zbc, int tx, int ty,
+                       int tz, uint8_t *flags) {
+    int tnx = (nx + tx - 1) / tx, tny = (ny + ty - 1) / ty;
     int32_t *b = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)N);
     orc_base_cells(N, q, nx, ny, b);
     for (int j = 0; j < N; ++j)
@@ -493,7 +493,7 @@ void orc_touched_tiles(int N, const double *q, int nx, int ny, int nz, int zbc, 
             for (int dy = -1; dy <= 2; ++dy)
                 for (int dx = -1; dx <= 2; ++dx) {
                     int ix = wrap(b[3 * j] + dx, nx), iy = wrap(b[3 * j + 1] + dy, ny);
-                    flags[((size_t)(kz / tile) * tny + iy / tile) * tnx + ix / tile] = 1;
+                    flags[((size_t)(kz / tz) * tny + iy / ty) * tnx + ix / tx] = 1;
                 }
         }
     free(b);

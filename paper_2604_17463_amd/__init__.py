@@ -5,5 +5,5 @@ include/iblb.h); this package only marshals arguments to it.
 """
 from .binding import (  # noqa: F401
     EXPORTS, IBLB_BF16DEV, IBLB_F16DEV, IBLB_F32, IBLB_F64, IBLB_FLAG_AUTOTUNE, IBLB_FLAG_FULL_U,
-    IBLB_FLAG_GRAPH, IblbError, Simulation, load, make_config, velocity_set, workspace_size,
+    IBLB_FLAG_GRAPH, IblbError, Simulation, band_tile, load, make_config, velocity_set, workspace_size,
 )

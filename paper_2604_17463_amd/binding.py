@@ -23,7 +23,7 @@ EXPORTS = (
     "iblb_velocity_set", "iblb_workspace_size", "iblb_init", "iblb_step", "iblb_observables",
     "iblb_read_state", "iblb_write_state", "iblb_read_nodes", "iblb_write_nodes",
     "iblb_compute_forces", "iblb_compute_spread", "iblb_interpolate", "iblb_read_bins",
-    "iblb_read_csr", "iblb_set_launch", "iblb_get_launch", "iblb_time_stream_collide",
+    "iblb_read_csr", "iblb_set_launch", "iblb_get_launch", "iblb_band_tile", "iblb_time_stream_collide",
     "iblb_destroy", "iblb_last_error",
 )
 
@@ -93,6 +93,7 @@ def load():
     L.iblb_read_csr.argtypes = [vp, i32, ip, ip]
     L.iblb_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
     L.iblb_get_launch.argtypes = [vp, ip, ip, ip, ip, ip]
+    L.iblb_band_tile.argtypes = [ip]
     L.iblb_time_stream_collide.argtypes = [vp, i32, dp]
     L.iblb_destroy.argtypes = [vp]
     L.iblb_last_error.argtypes = [vp]
@@ -151,6 +152,13 @@ def make_config(workload, storage=None, flags=0, dev_scale=None):
                                 _dptr(nodes), _iptr(tris), d.sigma, d.theta_eq, d.xi, d.k_vol)
     cfg = iblb_config(nb, nd, boxes, drops if nd else None, storage, flags, float(dev_scale))
     return cfg, keep
+
+
+def band_tile():
+    """(x, y, z) cells of the band tiles that compute_spread's flags refer to."""
+    shape = (C.c_int32 * 3)()
+    check(load().iblb_band_tile(shape))
+    return tuple(shape)
 
 
 def workspace_size(cfg) -> int:
@@ -246,7 +254,8 @@ class Simulation:
     def compute_spread(self, b=0):
         nz, ny, nx = self._box(b)
         F = np.empty((3, nz, ny, nx))
-        flags = np.zeros(((nz + 3) // 4, (ny + 3) // 4, (nx + 3) // 4), np.uint8)
+        tx, ty, tz = band_tile()
+        flags = np.zeros((-(-nz // tz), -(-ny // ty), -(-nx // tx)), np.uint8)
         self._chk(load().iblb_compute_spread(self.ctx, b, _dptr(F),
                                              flags.ctypes.data_as(C.POINTER(C.c_uint8))))
         return F, flags

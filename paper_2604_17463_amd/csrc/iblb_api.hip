@@ -183,9 +183,9 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
             return fail(err, IBLB_E_INVAL,
                         nm + ": box too large (ten population planes must fit in 4 GiB: at most " +
                             std::to_string(BUF_MAX_PLANE_GROUP / 10 / eb) + " cells incl. x padding)");
-        H.tnx = (B.nx + 3) / 4;
-        H.tny = (B.ny + 3) / 4;
-        H.tnz = (B.nz + 3) / 4;
+        H.tnx = (B.nx + TX - 1) / TX;
+        H.tny = (B.ny + TY - 1) / TY;
+        H.tnz = (B.nz + TZ - 1) / TZ;
         H.n_tiles = H.tnx * H.tny * H.tnz;
         H.tile_base = p.total_tiles;
         p.total_tiles += (int)round_up((size_t)H.n_tiles, TILE_CELLS);
@@ -575,9 +575,7 @@ iblb_status autotune(iblb_ctx *c) {
     //    leave CU slots to the mesh kernels that run beside it, at some cost
     //    in bulk bandwidth.  Each candidate starts from the initial state.
     if (c->plan.nblk > 0 && (c->plan.flags & IBLB_FLAG_GRAPH)) {
-        int dev = 0, cus = 0;
-        HIPCHK(c, hipGetDevice(&dev));
-        HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int cus = c->P.n_cus;
         const int wpg = best.bx * best.by / 64;  // waves per workgroup
         double sbest = 1e300;
         Launch chosen = best;
@@ -744,6 +742,12 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     P.n_chunks = p.n_chunks;
     P.total_tiles = p.total_tiles;
     P.obs_groups = OBS_GROUPS;
+    {
+        int dev = 0, cus = 0;
+        HIPCHK(c, hipGetDevice(&dev));
+        HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        P.n_cus = std::max(cus, 1);
+    }
 
     // host tables
     std::vector<BoxDev> bd(p.boxes.size());
@@ -1038,8 +1042,8 @@ iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_o
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
                     const size_t cell = ((size_t)z * ny + y) * nx + x;
-                    const size_t tile = ((size_t)(z >> 2) * H.tny + (y >> 2)) * H.tnx + (x >> 2);
-                    const int loc = ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
+                    const size_t tile = (size_t)band_tile(x, y, z, H.tnx, H.tny);
+                    const int loc = band_loc(x, y, z);
                     const bool ok = c->last_step_epoch >= 0 && stamp[tile] == c->last_step_epoch;
                     for (int a = 0; a < 3; ++a) {
                         const size_t k = (tile * 3 + a) * TILE_CELLS + loc;
@@ -1203,8 +1207,8 @@ iblb_status iblb_compute_spread(iblb_ctx *c, int32_t b, double *F_out, uint8_t *
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
                     const size_t cell = ((size_t)z * ny + y) * nx + x;
-                    const size_t tile = ((size_t)(z >> 2) * H.tny + (y >> 2)) * H.tnx + (x >> 2);
-                    const int loc = ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
+                    const size_t tile = (size_t)band_tile(x, y, z, H.tnx, H.tny);
+                    const int loc = band_loc(x, y, z);
                     for (int a = 0; a < 3; ++a) {
                         const size_t k = (tile * 3 + a) * TILE_CELLS + loc;
                         const double v = R == 8 ? ((double *)Fb.data())[k] : ((float *)Fb.data())[k];
@@ -1230,8 +1234,8 @@ iblb_status iblb_interpolate(iblb_ctx *c, int32_t d, const double *u_in, double 
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 const size_t cell = ((size_t)z * ny + y) * nx + x;
-                const size_t tile = ((size_t)(z >> 2) * H.tny + (y >> 2)) * H.tnx + (x >> 2);
-                const int loc = ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
+                const size_t tile = (size_t)band_tile(x, y, z, H.tnx, H.tny);
+                const int loc = band_loc(x, y, z);
                 for (int a = 0; a < 3; ++a) {
                     const size_t k = (tile * 3 + a) * TILE_CELLS + loc;
                     if (R == 8) ((double *)ub.data())[k] = u_in[(size_t)a * cells + cell];
@@ -1317,6 +1321,14 @@ iblb_status iblb_get_launch(const iblb_ctx *c, int32_t *bx, int32_t *by, int32_t
     *cpt = c->L.cpt;
     *nt = c->L.nt;
     *maxg = c->L.maxg;
+    return IBLB_OK;
+}
+
+iblb_status iblb_band_tile(int32_t *shape) {
+    if (!shape) return set_err(nullptr, IBLB_E_INVAL, "NULL argument");
+    shape[0] = TX;
+    shape[1] = TY;
+    shape[2] = TZ;
     return IBLB_OK;
 }
 

@@ -253,10 +253,11 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
         const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + tl[2 * i + 1];
         const int lt = gt - B->tile_base;
         const int tx = lt % B->tnx, ty = (lt / B->tnx) % B->tny, tz = lt / (B->tnx * B->tny);
-        const int x0 = tx * TILE, y0 = ty * TILE, z0 = tz * TILE;
-        const int x1 = min(x0 + TILE - 1, B->nx - 1), y1 = min(y0 + TILE - 1, B->ny - 1),
-                  z1 = min(z0 + TILE - 1, B->nz - 1);
-        const int cx = x0 + (lane & 3), cy = y0 + ((lane >> 2) & 3), cz = z0 + (lane >> 4);
+        const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+        const int x1 = min(x0 + TX - 1, B->nx - 1), y1 = min(y0 + TY - 1, B->ny - 1),
+                  z1 = min(z0 + TZ - 1, B->nz - 1);
+        const int cx = x0 + (lane & (TX - 1)), cy = y0 + ((lane >> TXS) & (TY - 1)),
+                  cz = z0 + (lane >> (TXS + TYS));
         const bool inside = cx < B->nx && cy < B->ny && cz < B->nz;
         // the populations are pulled first so that their loads are in flight
         // during the force gather

@@ -18,8 +18,21 @@
 namespace iblb {
 
 constexpr int Q = 19;
-constexpr int TILE = 4;
-constexpr int TILE_CELLS = 64;
+// Band tile: 16 consecutive cells along x, 4 along y, 1 along z (64 cells,
+// one wavefront).  Population rows are contiguous along x, so a tile reads
+// and writes 64-byte runs of each FP32 population row.
+constexpr int TX = 16, TY = 4, TZ = 1;
+constexpr int TXS = 4, TYS = 2, TZS = 0;  // log2 of the tile extents
+constexpr int TILE_CELLS = TX * TY * TZ;
+static_assert(TILE_CELLS == 64 && (1 << TXS) == TX && (1 << TYS) == TY && (1 << TZS) == TZ, "band tile");
+
+// Band tile of cell (x, y, z) and the cell's place in it.
+__host__ __device__ inline int64_t band_tile(int x, int y, int z, int tnx, int tny) {
+    return ((int64_t)(z >> TZS) * tny + (y >> TYS)) * tnx + (x >> TXS);
+}
+__host__ __device__ inline int band_loc(int x, int y, int z) {
+    return (((z & (TZ - 1)) << (TXS + TYS)) | ((y & (TY - 1)) << TXS) | (x & (TX - 1)));
+}
 constexpr int NB = 64;           // nodes per block
 constexpr int TRI_CHUNK = 256;   // triangles per FP64 partial-sum chunk
 constexpr int TREC = 20;         // per-triangle record: five four-vectors (A, n), (N/6, 0),
@@ -118,10 +131,10 @@ struct DevPtrs {
     double *obs_part;           // observables scratch
     double *obs_out;            // per droplet [12], per box [2]
     int32_t Ntot, nblk, Ttot, n_chunks;
-    int32_t n_rowgroups, total_tiles, obs_groups, pad;
+    int32_t n_rowgroups, total_tiles, obs_groups, n_cus;  // n_cus: compute units of the device
 };
 
-// Launch entry points implemented in iblb_kernels.hip.
+// Launch entry points (iblb_fluid.hip, iblb_mesh.hip).
 struct Launch {
     int bx, by;                 // bulk stream-collide block shape
     int grid;                   // bulk stream-collide grid (<= n_rowgroups)

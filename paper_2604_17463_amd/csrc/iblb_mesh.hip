@@ -106,10 +106,12 @@ __global__ void __launch_bounds__(64) k_set_v0(DevPtrs P) {
 // stencil points, so no two lanes touch the same cell; node data are read
 // from LDS as broadcasts), then writes that partial region out for the tile
 // gather.
-template <typename R>
-__global__ void __launch_bounds__(256) k_node(DevPtrs P, int mode) {
-    // NR waves spread NB / NR nodes each into their own LDS copy of the region
-    constexpr int NR = sizeof(R) == 4 ? 4 : 2;
+template <typename R, int NR>
+__global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
+    // NR waves spread NB / NR nodes each into their own LDS copy of the
+    // region (NR = 1 keeps the LDS small when there are many more blocks
+    // than compute units, NR > 1 shortens a block when there are few)
+    constexpr int NT = 64 * NR;
     __shared__ R reg[NR][3 * MAXP];
     __shared__ R nw[12][NB], nf[3][NB];
     __shared__ int nbs[3][NB];
@@ -238,7 +240,7 @@ __global__ void __launch_bounds__(256) k_node(DevPtrs P, int mode) {
                         int c = s0[a] + o;  // s0 is wrapped on periodic axes
                         if (per) c = c >= dims[a] ? c - dims[a] : c;
                         else if (c < 0 || c >= dims[a]) continue;
-                        const int tt = c >> 2;
+                        const int tt = c >> (a == 0 ? TXS : (a == 1 ? TYS : TZS));
                         if (tn[a] == 0 || tl[a][tn[a] - 1] != tt) tl[a][tn[a]++] = tt;
                     }
                 }
@@ -299,7 +301,7 @@ __global__ void __launch_bounds__(256) k_node(DevPtrs P, int mode) {
     const int ex = sreg[0], ey = sreg[1], ez = sreg[2];
     if (sreg[3]) return;
     const int ncell = ex * ey * ez, nvalid = sreg[4];
-    for (int c = tid; c < ncell; c += 256)
+    for (int c = tid; c < ncell; c += NT)
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             reg[r][c] = R(0);
@@ -330,7 +332,7 @@ __global__ void __launch_bounds__(256) k_node(DevPtrs P, int mode) {
     __syncthreads();
     // block partial = region 0 + region 1 + ... (fixed order)
     IBLB_GLOBAL R *out = (IBLB_GLOBAL R *)P.part + (int64_t)blk * 3 * MAXP;
-    for (int c = tid; c < ncell; c += 256)
+    for (int c = tid; c < ncell; c += NT)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             R v = reg[0][k * MAXP + c];
@@ -396,8 +398,7 @@ __global__ void __launch_bounds__(256) k_interp(DevPtrs P, int mode, double *Uou
     const int ex = bx1 - bx0 + 1, ey = by1 - by0 + 1, ez = bz1 - bz0 + 1;
     const bool staged = ex > 0 && ey > 0 && ez > 0 && (int64_t)ex * ey * ez <= MAXR;
     auto gidx = [&](int x, int y, int z) -> int64_t {
-        const int64_t tile = ((int64_t)(z >> 2) * B.tny + (y >> 2)) * B.tnx + (x >> 2);
-        return tile * 3 * TILE_CELLS + (((z & 3) << 4) | ((y & 3) << 2) | (x & 3));
+        return band_tile(x, y, z, B.tnx, B.tny) * 3 * TILE_CELLS + band_loc(x, y, z);
     };
     if (staged) {
         const int x0w = wrapn(bx0, B.nx);
@@ -625,8 +626,16 @@ hipError_t launch_set_v0(const DevPtrs &P, bool, hipStream_t s) {
 
 hipError_t launch_node(const DevPtrs &P, bool f64, int mode, hipStream_t s) {
     if (P.nblk == 0) return hipSuccess;
-    if (f64) hipLaunchKernelGGL(k_node<double>, dim3(P.nblk), dim3(256), 0, s, P, mode);
-    else hipLaunchKernelGGL(k_node<float>, dim3(P.nblk), dim3(256), 0, s, P, mode);
+    // few blocks: several waves per block share its spread; many blocks:
+    // one wave per block, so that more blocks fit in a compute unit's LDS
+    const bool many = P.nblk > P.n_cus;
+    if (f64) {
+        if (many) hipLaunchKernelGGL((k_node<double, 1>), dim3(P.nblk), dim3(64), 0, s, P, mode);
+        else hipLaunchKernelGGL((k_node<double, 2>), dim3(P.nblk), dim3(128), 0, s, P, mode);
+    } else {
+        if (many) hipLaunchKernelGGL((k_node<float, 1>), dim3(P.nblk), dim3(64), 0, s, P, mode);
+        else hipLaunchKernelGGL((k_node<float, 4>), dim3(P.nblk), dim3(256), 0, s, P, mode);
+    }
     if (mode == 0 && P.total_tiles > 0) {
         const int chunks = P.total_tiles / TILE_CELLS;
         hipLaunchKernelGGL(k_compact, dim3((chunks + 3) / 4), dim3(256), 0, s, P);

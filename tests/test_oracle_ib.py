@@ -115,12 +115,15 @@ def test_base_cells_brute_force():
             assert b[j, a] == want
 
 
-def test_touched_tiles_brute_force():
+@pytest.mark.parametrize("tile", [(4, 4, 4), (16, 4, 1), (3, 5, 2)])
+def test_touched_tiles_brute_force(tile):
     shape = (16, 16, 12)
     nz, ny, nx = shape
+    tx, ty, tz = tile
     q = np.column_stack([RNG.uniform(-5, 20, 25), RNG.uniform(0, 16, 25), RNG.uniform(0.2, 15.8, 25)])
     for zbc in (0, 1):
-        flags = oracle.touched_tiles(q, shape, zbc, tile=4)
+        flags = oracle.touched_tiles(q, shape, zbc, tile=tile)
+        assert flags.shape == (-(-nz // tz), -(-ny // ty), -(-nx // tx))
         want = np.zeros_like(flags)
         for p in q:
             base = [int(np.floor(p[a] - 0.5)) for a in range(3)]
@@ -130,5 +133,5 @@ def test_touched_tiles_brute_force():
                     continue
                 for dy in range(-1, 3):
                     for dx in range(-1, 3):
-                        want[(k % nz) // 4, ((base[1] + dy) % ny) // 4, ((base[0] + dx) % nx) // 4] = 1
+                        want[(k % nz) // tz, ((base[1] + dy) % ny) // ty, ((base[0] + dx) % nx) // tx] = 1
         assert np.array_equal(flags, want)
