@@ -58,7 +58,7 @@ struct Plan {
            off_trec = 0, off_tile_list = 0, off_tile_count = 0, off_part = 0, off_breg = 0,
            off_base = 0, off_s0 = 0, off_bbox = 0, off_blk_drop = 0, off_tri = 0,
            off_csr_off = 0, off_csr_ent = 0, off_chunks = 0, off_tri_part = 0, off_rows = 0,
-           off_tchunk = 0, off_ctr = 0, off_status = 0, off_obs_part = 0, off_obs_out = 0,
+           off_tchunk = 0, off_tcand = 0, off_tncand = 0, off_scan = 0, off_ctr = 0, off_status = 0, off_obs_part = 0, off_obs_out = 0,
            off_uout = 0, total = 0;
 };
 
@@ -313,6 +313,9 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
     p.off_tri_part = take(2 * (size_t)p.n_chunks * 8);
     p.off_rows = take(sizeof(RowGroup) * (size_t)p.max_rows);
     p.off_tchunk = take((size_t)(p.total_tiles / TILE_CELLS) * 4);
+    p.off_tcand = take((size_t)p.total_tiles * MAXC * 4);
+    p.off_tncand = take((size_t)2 * p.total_tiles * 4);
+    p.off_scan = take((size_t)2 * p.boxes.size() * 4);
     p.off_ctr = take(4);
     p.off_status = take(4);
     p.off_obs_part = take(2 * (size_t)OBS_GROUPS * 8);
@@ -732,6 +735,9 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     P.tri_part = (double *)at(p.off_tri_part);
     P.rows = (RowGroup *)at(p.off_rows);
     P.tchunk_box = (int32_t *)at(p.off_tchunk);
+    P.tcand = (int32_t *)at(p.off_tcand);
+    P.tncand = (int32_t *)at(p.off_tncand);
+    P.scan_all = (int32_t *)at(p.off_scan);
     P.ctr = (int32_t *)at(p.off_ctr);
     P.status = (uint32_t *)at(p.off_status);
     P.obs_part = (double *)at(p.off_obs_part);
@@ -873,6 +879,8 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     }
     HIPCHK(c, hipMemsetAsync(P.ctr, 0, 4, c->stream));
     HIPCHK(c, hipMemsetAsync(P.tile_count, 0, 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(P.tncand, 0, (size_t)2 * p.total_tiles * 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(P.scan_all, 0, (size_t)2 * p.boxes.size() * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(P.status, 0, 4, c->stream));
     HIPCHK(c, hipMemsetAsync(P.phi, 0, (size_t)3 * N * R, c->stream));
     // reference volumes V0 from the initial mesh (same FP64 sum as the penalty)

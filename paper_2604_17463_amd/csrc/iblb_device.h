@@ -374,8 +374,11 @@ template <int AUX> __device__ __forceinline__ void bstore(__bf16 x, __amdgpu_buf
     __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, x), r, v, s, AUX);
 }
 
-// pull_raw through buffer resources, for a wave whose lanes share `ra`.
-template <int ST>
+// pull_raw through buffer resources.  ROWV = false: the lanes of the wave
+// share `ra`, so the row goes into the scalar offset with the plane; true:
+// each lane has its own row, added to its per-lane offset (32-bit, so a
+// lane holds no 64-bit addresses).
+template <int ST, bool ROWV = false>
 __device__ __forceinline__ void pull_buf(const PopRes &rs, uint32_t pb, const RowAddr &ra, const XOff &xo,
                                          typename Stor<ST>::R (&g)[Q]) {
     using T = typename Stor<ST>::T;
@@ -383,23 +386,44 @@ __device__ __forceinline__ void pull_buf(const PopRes &rs, uint32_t pb, const Ro
     for (int i = 0; i < Q; ++i) {
         const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
         const int o = opp_of(i);
-        const bool bb = (cz == 1 && ra.wlo) || (cz == -1 && ra.whi);
-        const __amdgpu_buffer_rsrc_t r = bb ? (o < 10 ? rs.lo : rs.hi) : (i < 10 ? rs.lo : rs.hi);
-        const uint32_t so = bb ? (uint32_t)(o % 10) * pb + ra.ro[1][1]
-                               : (uint32_t)(i % 10) * pb + ra.ro[cy + 1][cz + 1];
-        const uint32_t vo = bb ? xo.c : (cx == 1 ? xo.m : (cx == -1 ? xo.p : xo.c));
-        g[i] = (typename Stor<ST>::R)bload<T>(r, vo, so);
+        const uint32_t xv = cx == 1 ? xo.m : (cx == -1 ? xo.p : xo.c);
+        if constexpr (ROWV) {
+            // a wall population reads the opposite one at the cell itself;
+            // the planes i and opp(i) lie in different halves, so both loads
+            // are issued and the lane keeps the one it needs
+            if (cz == 0) {
+                g[i] = (typename Stor<ST>::R)bload<T>(i < 10 ? rs.lo : rs.hi, ra.ro[cy + 1][1] + xv,
+                                                      (uint32_t)(i % 10) * pb);
+            } else {
+                const bool bb = (cz == 1 && ra.wlo) || (cz == -1 && ra.whi);
+                const T a = bload<T>(i < 10 ? rs.lo : rs.hi, ra.ro[cy + 1][cz + 1] + xv, (uint32_t)(i % 10) * pb);
+                const T b = bload<T>(o < 10 ? rs.lo : rs.hi, ra.ro[1][1] + xo.c, (uint32_t)(o % 10) * pb);
+                g[i] = (typename Stor<ST>::R)(bb ? b : a);
+            }
+        } else {
+            const bool bb = (cz == 1 && ra.wlo) || (cz == -1 && ra.whi);
+            const __amdgpu_buffer_rsrc_t r = bb ? (o < 10 ? rs.lo : rs.hi) : (i < 10 ? rs.lo : rs.hi);
+            const uint32_t so = bb ? (uint32_t)(o % 10) * pb + ra.ro[1][1]
+                                   : (uint32_t)(i % 10) * pb + ra.ro[cy + 1][cz + 1];
+            const uint32_t vo = bb ? xo.c : xv;
+            g[i] = (typename Stor<ST>::R)bload<T>(r, vo, so);
+        }
     }
 }
 
-// store_ptr through buffer resources; `own_row` is the wave's row offset.
-template <int ST, bool NT>
+// store_ptr through buffer resources; `own_row` is the row offset, scalar
+// (ROWV = false) or per lane (ROWV = true).
+template <int ST, bool NT, bool ROWV = false>
 __device__ __forceinline__ void store_buf(const PopRes &rd, uint32_t pb, uint32_t own_row, uint32_t xoc,
                                           const typename Stor<ST>::R (&out)[Q]) {
     using T = typename Stor<ST>::T;
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-        bstore<NT ? 2 : 0>((T)out[i], i < 10 ? rd.lo : rd.hi, xoc, (uint32_t)(i % 10) * pb + own_row);
+    for (int i = 0; i < Q; ++i) {
+        if constexpr (ROWV)
+            bstore<NT ? 2 : 0>((T)out[i], i < 10 ? rd.lo : rd.hi, own_row + xoc, (uint32_t)(i % 10) * pb);
+        else
+            bstore<NT ? 2 : 0>((T)out[i], i < 10 ? rd.lo : rd.hi, xoc, (uint32_t)(i % 10) * pb + own_row);
+    }
 }
 
 }  // namespace iblb

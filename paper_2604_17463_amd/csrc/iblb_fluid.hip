@@ -97,24 +97,27 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
 }
 
 // ------------------------------------------------------------ spread gather
-// Spread force density (Eq. 8) at cell (cx,cy,cz) of the tile [x0..x1] x
-// [y0..y1] x [z0..z1], for the calling lane.  Node blocks whose stencil box
-// meets the tile contribute in ascending block order; a block's own
-// contribution is the partial sum its node pass accumulated over its nodes
-// (read from the block's partial region), or, for a block whose region did
-// not fit, the nodes summed here one by one in ascending order.  No
-// atomics: the sum order per cell is fixed.
+// Spread force density (Eq. 8) at cell (cx,cy,cz) of band tile gt ([x0..x1]
+// x [y0..y1] x [z0..z1]) of box `box`, for the calling lane.  The node
+// blocks whose stencil box covers the tile contribute in ascending block
+// order; a block's own contribution is the partial sum its node pass
+// accumulated over its nodes (read from the block's partial region), or,
+// for a block whose region did not fit, the nodes summed here one by one in
+// ascending order.  No atomics: the sum order per cell is fixed.
 //
-// Latency: the bounding boxes of GATHER_GROUP x 64 blocks are tested with
-// their loads in flight together; the hits go to a wave-private LDS list in
-// ascending order and are then read back eight at a time, so region
-// descriptors and partial values of eight blocks load side by side.
+// The candidate blocks are the ones the node pass recorded for the tile
+// (sorted here); when the records are incomplete the bounding boxes of all
+// blocks of the box are tested, GATHER_GROUP x 64 at a time, their hits
+// going to a wave-private LDS list in ascending order.  Either way the
+// region descriptors and partial values of GATHER_BATCH blocks load side by
+// side.
 constexpr int GATHER_GROUP = 4;
+constexpr int GATHER_BATCH = 4;
 
 template <typename R>
-__device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxDev *B, int x0, int x1,
-                                         int y0, int y1, int z0, int z1, int cx, int cy, int cz,
-                                         int *hits, R &F0, R &F1, R &F2) {
+__device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxDev *B, int box, int gt,
+                                         int slot, int x0, int x1, int y0, int y1, int z0, int z1, int cx,
+                                         int cy, int cz, int *hits, R &F0, R &F1, R &F2) {
     const int lane = threadIdx.x & 63;
     const uint64_t below = (1ull << lane) - 1ull;
     const int nb = P.nblk, N = P.Ntot;
@@ -123,6 +126,113 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
     const int b0 = B->blk_begin, b1 = B->blk_end;
     const IBLB_GLOBAL R *part = (const IBLB_GLOBAL R *)P.part;
     const IBLB_CONST int32_t *breg = (const IBLB_CONST int32_t *)P.breg;
+
+    // add the contributions of blocks id(0..n) (ascending) to F: the blocks
+    // with a partial region in order, then those without one (their nodes
+    // one by one), also in order
+    auto add_blocks = [&](auto id, int n) {
+        R v[GATHER_BATCH][3];
+        bool ovf[GATHER_BATCH];
+        bool any_ovf = false;
+#pragma unroll
+        for (int k = 0; k < GATHER_BATCH; ++k) {
+            v[k][0] = v[k][1] = v[k][2] = R(0);
+            ovf[k] = false;
+            if (k < n) {
+                const int blk = id(k);
+                const IBLB_CONST int32_t *br = breg + (int64_t)blk * BREG;
+                ovf[k] = br[6] != 0;
+                any_ovf |= ovf[k];
+                if (!ovf[k]) {
+                    int dx = cx - br[0], dy = cy - br[1], dz = cz - br[2];
+                    if (dx < 0) dx += nx;
+                    if (dy < 0) dy += ny;
+                    if (zper && dz < 0) dz += nz;
+                    const int ex = br[3], ey = br[4], ez = br[5];
+                    if (dx < ex && dy < ey && dz >= 0 && dz < ez) {
+                        const int64_t c = (int64_t)blk * 3 * MAXP + (dz * ey + dy) * ex + dx;
+                        v[k][0] = part[c];
+                        v[k][1] = part[c + MAXP];
+                        v[k][2] = part[c + 2 * MAXP];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < GATHER_BATCH; ++k) {
+            if (k < n && !ovf[k]) {
+                F0 += v[k][0];
+                F1 += v[k][1];
+                F2 += v[k][2];
+            }
+        }
+        if (!any_ovf) return;
+#pragma unroll 1
+        for (int k = 0; k < n; ++k) {
+            const int blk = id(k);
+            if (breg[(int64_t)blk * BREG + 6] == 0) continue;
+            const DropDev &D = P.drops[P.blk_drop[2 * blk]];
+            const int j = blk * NB + lane;
+            bool nh = false;
+            if (j - D.node_off < D.n_nodes) {
+                const int bx = P.base[j], by = P.base[N + j], bz = P.base[2 * N + j];
+                nh = meets(bx - 1, bx + 2, x0, x1, nx, true) && meets(by - 1, by + 2, y0, y1, ny, true) &&
+                     meets(bz - 1, bz + 2, z0, z1, nz, zper);
+            }
+            uint64_t nmask = __ballot(nh);
+            if (!nmask) continue;
+            const R *wgt = (const R *)P.wgt, *phi = (const R *)P.phi;
+            int s0x = 0, s0y = 0, s0z = 0;
+            R w[12], f[3];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) w[q] = 0;
+            f[0] = f[1] = f[2] = 0;
+            if (nh) {
+                s0x = P.s0[j];
+                s0y = P.s0[N + j];
+                s0z = P.s0[2 * N + j];
+#pragma unroll
+                for (int q = 0; q < 12; ++q) w[q] = wgt[q * N + j];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) f[q] = phi[q * N + j];
+            }
+            while (nmask) {
+                const int nl = __builtin_ctzll(nmask);
+                nmask &= nmask - 1;
+                int ox = cx - bcast_i(s0x, nl), oy = cy - bcast_i(s0y, nl), oz = cz - bcast_i(s0z, nl);
+                if (ox < 0) ox += nx;
+                if (oy < 0) oy += ny;
+                if (zper && oz < 0) oz += nz;
+                const R ax = pick4(ox, bcast(w[0], nl), bcast(w[1], nl), bcast(w[2], nl), bcast(w[3], nl));
+                const R ay = pick4(oy, bcast(w[4], nl), bcast(w[5], nl), bcast(w[6], nl), bcast(w[7], nl));
+                const R az = pick4(oz, bcast(w[8], nl), bcast(w[9], nl), bcast(w[10], nl), bcast(w[11], nl));
+                const R wv = ax * ay * az;
+                F0 += bcast(f[0], nl) * wv;
+                F1 += bcast(f[1], nl) * wv;
+                F2 += bcast(f[2], nl) * wv;
+            }
+        }
+    };
+
+    // the recorded candidates: count, flag and the MAXC slots (lane k holds
+    // slot k) in one round trip
+    const int ncand = ((const IBLB_CONST int32_t *)P.tncand)[(int64_t)slot * P.total_tiles + gt];
+    const bool scan = ((const IBLB_CONST int32_t *)P.scan_all)[slot * P.n_boxes + box] != 0;
+    int mine = lane < MAXC ? P.tcand[(int64_t)gt * MAXC + lane] : INT_MAX;
+    if (!scan && ncand <= MAXC) {
+        mine = lane < ncand ? mine : INT_MAX;
+        // rank of each lane's block among the candidates (the ids are distinct)
+        int rank = 0;
+        for (int k = 0; k < ncand; ++k) rank += __builtin_amdgcn_readlane(mine, k) < mine ? 1 : 0;
+        for (int r0 = 0; r0 < ncand; r0 += GATHER_BATCH) {
+            auto id = [&](int k) {
+                const uint64_t m = __ballot(lane < ncand && rank == r0 + k);
+                return m ? __builtin_amdgcn_readlane(mine, __builtin_ctzll(m)) : 0;
+            };
+            add_blocks(id, min(GATHER_BATCH, ncand - r0));
+        }
+        return;
+    }
     for (int kb = b0; kb < b1; kb += 64 * GATHER_GROUP) {
         bool hit[GATHER_GROUP];
 #pragma unroll
@@ -143,88 +253,9 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int k0 = 0; k0 < total; k0 += 8) {
-            const int n = min(8, total - k0);
-            int ids[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) ids[k] = __builtin_amdgcn_readfirstlane(k < n ? hits[k0 + k] : 0);
-            R v[8][3];
-            bool ovf[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                v[k][0] = v[k][1] = v[k][2] = R(0);
-                ovf[k] = false;
-                if (k < n) {
-                    const IBLB_CONST int32_t *br = breg + (int64_t)ids[k] * BREG;
-                    ovf[k] = br[6] != 0;
-                    if (!ovf[k]) {
-                        int dx = cx - br[0], dy = cy - br[1], dz = cz - br[2];
-                        if (dx < 0) dx += nx;
-                        if (dy < 0) dy += ny;
-                        if (zper && dz < 0) dz += nz;
-                        const int ex = br[3], ey = br[4], ez = br[5];
-                        if (dx < ex && dy < ey && dz >= 0 && dz < ez) {
-                            const int64_t c = (int64_t)ids[k] * 3 * MAXP + (dz * ey + dy) * ex + dx;
-                            v[k][0] = part[c];
-                            v[k][1] = part[c + MAXP];
-                            v[k][2] = part[c + 2 * MAXP];
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (k >= n) break;
-                if (!ovf[k]) {
-                    F0 += v[k][0];
-                    F1 += v[k][1];
-                    F2 += v[k][2];
-                    continue;
-                }
-                // block without a partial region: its nodes one by one
-                const int blk = ids[k];
-                const DropDev &D = P.drops[P.blk_drop[2 * blk]];
-                const int j = blk * NB + lane;
-                bool nh = false;
-                if (j - D.node_off < D.n_nodes) {
-                    const int bx = P.base[j], by = P.base[N + j], bz = P.base[2 * N + j];
-                    nh = meets(bx - 1, bx + 2, x0, x1, nx, true) &&
-                         meets(by - 1, by + 2, y0, y1, ny, true) &&
-                         meets(bz - 1, bz + 2, z0, z1, nz, zper);
-                }
-                uint64_t nmask = __ballot(nh);
-                if (!nmask) continue;
-                const R *wgt = (const R *)P.wgt, *phi = (const R *)P.phi;
-                int s0x = 0, s0y = 0, s0z = 0;
-                R w[12], f[3];
-#pragma unroll
-                for (int q = 0; q < 12; ++q) w[q] = 0;
-                f[0] = f[1] = f[2] = 0;
-                if (nh) {
-                    s0x = P.s0[j];
-                    s0y = P.s0[N + j];
-                    s0z = P.s0[2 * N + j];
-#pragma unroll
-                    for (int q = 0; q < 12; ++q) w[q] = wgt[q * N + j];
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) f[q] = phi[q * N + j];
-                }
-                while (nmask) {
-                    const int nl = __builtin_ctzll(nmask);
-                    nmask &= nmask - 1;
-                    int ox = cx - bcast_i(s0x, nl), oy = cy - bcast_i(s0y, nl), oz = cz - bcast_i(s0z, nl);
-                    if (ox < 0) ox += nx;
-                    if (oy < 0) oy += ny;
-                    if (zper && oz < 0) oz += nz;
-                    const R ax = pick4(ox, bcast(w[0], nl), bcast(w[1], nl), bcast(w[2], nl), bcast(w[3], nl));
-                    const R ay = pick4(oy, bcast(w[4], nl), bcast(w[5], nl), bcast(w[6], nl), bcast(w[7], nl));
-                    const R az = pick4(oz, bcast(w[8], nl), bcast(w[9], nl), bcast(w[10], nl), bcast(w[11], nl));
-                    const R wv = ax * ay * az;
-                    F0 += bcast(f[0], nl) * wv;
-                    F1 += bcast(f[1], nl) * wv;
-                    F2 += bcast(f[2], nl) * wv;
-                }
-            }
+        for (int k0 = 0; k0 < total; k0 += GATHER_BATCH) {
+            auto id = [&](int k) { return __builtin_amdgcn_readfirstlane(hits[k0 + k]); };
+            add_blocks(id, min(GATHER_BATCH, total - k0));
         }
         __builtin_amdgcn_wave_barrier();  // the list is rewritten by the next group
     }
@@ -249,8 +280,8 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
     const int count = min((ctr & 1) ? n1 : n0, P.total_tiles);
     const IBLB_CONST int32_t *tl = (const IBLB_CONST int32_t *)P.tile_list;
     for (int i = wave; i < count; i += nwaves) {
-        const int gt = tl[2 * i];  // global tile id and its box
-        const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + tl[2 * i + 1];
+        const int gt = tl[2 * i], box = tl[2 * i + 1];  // global tile id and its box
+        const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + box;
         const int lt = gt - B->tile_base;
         const int tx = lt % B->tnx, ty = (lt / B->tnx) % B->tny, tz = lt / (B->tnx * B->tny);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
@@ -262,17 +293,18 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
         // the populations are pulled first so that their loads are in flight
         // during the force gather
         const uint64_t pb = (uint64_t)B->plane * EB;
-        const IBLB_GLOBAL char *src = (const IBLB_GLOBAL char *)B->f[parity];
+        const PopRes rs = pop_res(B->f[parity], pb);
         RowAddr ra{};
         XOff xo{};
         R g[Q];
         if (COLLIDE && inside) {
             ra = row_addr(cy, cz, B->ny, B->nz, B->sx, B->zbc == 1, EB);
             xo = x_off<EB>(cx, B->nx);
-            pull_raw<ST>(src, pb, ra, xo, g);
+            pull_buf<ST, true>(rs, (uint32_t)pb, ra, xo, g);
         }
         R F0 = 0, F1 = 0, F2 = 0;
-        gather_F<R>(P, B, x0, x1, y0, y1, z0, z1, cx, cy, cz, hits[threadIdx.x >> 6], F0, F1, F2);
+        gather_F<R>(P, B, box, gt, ctr & 1, x0, x1, y0, y1, z0, z1, cx, cy, cz, hits[threadIdx.x >> 6], F0,
+                    F1, F2);
         if (!COLLIDE) {
             IBLB_GLOBAL R *Fb = (IBLB_GLOBAL R *)B->Fband + (int64_t)lt * 3 * TILE_CELLS;
             Fb[lane] = F0;
@@ -281,12 +313,11 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
             continue;
         }
         if (!inside) continue;
-        IBLB_GLOBAL char *dst = (IBLB_GLOBAL char *)B->f[parity ^ 1];
         R out[Q], u[3], rho;
         const uint32_t own = ra.ro[1][1] + xo.c;
         collide<ST>(g, (R)B->g[0] + F0, (R)B->g[1] + F1, (R)B->g[2] + F2, (R)B->rho0, (R)B->omega,
                     (R)B->guo, scale, inv, out, u, rho);
-        store_ptr<ST, false>(dst, pb, own, out);
+        store_buf<ST, false, true>(pop_res(B->f[parity ^ 1], pb), (uint32_t)pb, ra.ro[1][1], xo.c, out);
         IBLB_GLOBAL R *ub = (IBLB_GLOBAL R *)B->uband + (int64_t)lt * 3 * TILE_CELLS;
         ub[lane] = u[0];
         ub[TILE_CELLS + lane] = u[1];

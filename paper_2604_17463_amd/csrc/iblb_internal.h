@@ -40,7 +40,8 @@ constexpr int TREC = 20;         // per-triangle record: five four-vectors (A, n
 static_assert(TREC == 5 * 4, "triangle record = five four-vectors");
 constexpr int K1_MAX_THREADS = 256; // launch bound of the bulk stream-collide kernel
 constexpr int MAXP = 2048;          // cells of a node block's partial-spread region
-constexpr int BREG = 8;             // ints per block region descriptor
+constexpr int BREG = 8;
+constexpr int MAXC = 16;           // node blocks recorded per band tile (more: the gather scans)             // ints per block region descriptor
 
 // Velocity set in the library's order: 0 = rest, i and i+9 opposite (i=1..9).
 __host__ __device__ constexpr int cx_of(int i) {
@@ -126,6 +127,9 @@ struct DevPtrs {
     double *tri_part;           // [2][n_chunks]: volume, area
     RowGroup *rows;
     int32_t *tchunk_box;        // [total_tiles/64] box of each 64-tile chunk
+    int32_t *tcand;             // [total_tiles][MAXC] node blocks whose stencil box covers the tile
+    int32_t *tncand;            // [2][total_tiles] their number, by epoch parity
+    int32_t *scan_all;          // [2][n_boxes] some block of the box could not record its tiles
     int32_t *ctr;               // step epoch
     uint32_t *status;
     double *obs_part;           // observables scratch

@@ -116,6 +116,7 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
     __shared__ R nw[12][NB], nf[3][NB];
     __shared__ int nbs[3][NB];
     __shared__ int sreg[5];  // ex, ey, ez, overflow, nodes in the block
+    __shared__ int tlist[3][64];  // distinct tiles per axis of the block's stencil box
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int blk = blockIdx.x;
     // droplet and box in one load, so their records load side by side
@@ -125,7 +126,7 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
         const BoxDev &B = P.boxes[bi];
         // every constant of the droplet and its box is read here, before the
         // first store (a scalar load behind vector stores waits for them)
-        const int nx = B.nx, ny = B.ny, nz = B.nz, tnx = B.tnx, tny = B.tny;
+        const int nx = B.nx, ny = B.ny, nz = B.nz, tnx = B.tnx, tny = B.tny, tile_base = B.tile_base;
         const bool zper = B.zbc == 1;
         IBLB_GLOBAL int32_t *const stamp = (IBLB_GLOBAL int32_t *)B.stamp;
         const int node_off = D.node_off, n_nodes = D.n_nodes, n_exp = D.n_exp, m_exp = D.m_exp;
@@ -271,6 +272,51 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
         const int ex = bh[0] - bl[0] + 1, ey = bh[1] - bl[1] + 1, ez = zh - zl + 1;
         const bool ovf = ex > nx || ey > ny || (zper && ez > nz) || ez < 1 ||
                          (int64_t)ex * ey * ez > MAXP;
+        // every band tile that the stencil box covers records the block (slot
+        // from an integer counter; the gather sorts the ids, so the order of
+        // the records does not matter); a block whose box spans more than 64
+        // cells on an axis, or a periodic axis whole, makes its box's gather scan
+        {
+            const int slot = ctr & 1;
+            const int lo3[3] = {bl[0], bl[1], zl}, hi3[3] = {bh[0], bh[1], zh};
+            int ntl[3];
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int span = hi3[a] - lo3[a] + 1;
+                const bool per = a < 2 || zper;
+                if (span < 1 || span > 64 || (per && span > dims[a])) {
+                    ok = false;
+                    ntl[a] = 0;
+                    continue;
+                }
+                int t = -1;
+                if (lane < span) {
+                    int cc = lo3[a] + lane;
+                    if (per) cc = wrapn(cc, dims[a]);
+                    t = cc >> (a == 0 ? TXS : (a == 1 ? TYS : TZS));
+                }
+                const int tprev = __shfl_up(t, 1, 64);
+                const bool first = lane < span && (lane == 0 || t != tprev);
+                const uint64_t m = __ballot(first);
+                ntl[a] = __popcll(m);
+                if (first) tlist[a][__popcll(m & ((1ull << lane) - 1ull))] = t;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (ok) {
+                const int nt = ntl[0] * ntl[1] * ntl[2];
+                for (int k = lane; k < nt; k += 64) {
+                    const int ix = k % ntl[0], iy = (k / ntl[0]) % ntl[1], iz = k / (ntl[0] * ntl[1]);
+                    const int gt = tile_base + (tlist[2][iz] * tny + tlist[1][iy]) * tnx + tlist[0][ix];
+                    const int pos = atomicAdd(P.tncand + (int64_t)slot * P.total_tiles + gt, 1);
+                    if (pos < MAXC) P.tcand[(int64_t)gt * MAXC + pos] = blk;
+                }
+            } else if (lane == 0) {
+                P.scan_all[slot * P.n_boxes + bi] = 1;
+            }
+        }
         if (lane == 0) {
             int32_t *br = P.breg + (int64_t)blk * BREG;
             br[0] = wrapn(bl[0], nx);
@@ -351,8 +397,13 @@ __global__ void __launch_bounds__(256) k_compact(DevPtrs P) {
     const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int ctr = *P.ctr;
     const int slot = ctr & 1;
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.tile_count[slot ^ 1] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P.tile_count[slot ^ 1] = 0;
+        for (int b = 0; b < P.n_boxes; ++b) P.scan_all[(slot ^ 1) * P.n_boxes + b] = 0;
+    }
     if (c >= P.total_tiles / TILE_CELLS) return;
+    // the next epoch's tile records start empty
+    P.tncand[(int64_t)(slot ^ 1) * P.total_tiles + c * TILE_CELLS + lane] = 0;
     const int box = P.tchunk_box[c];
     const BoxDev &B = P.boxes[box];
     const int lt = c * TILE_CELLS + lane - B.tile_base;
@@ -401,19 +452,37 @@ __global__ void __launch_bounds__(256) k_interp(DevPtrs P, int mode, double *Uou
         return band_tile(x, y, z, B.tnx, B.tny) * 3 * TILE_CELLS + band_loc(x, y, z);
     };
     if (staged) {
-        const int x0w = wrapn(bx0, B.nx);
-        for (int r = tid >> 4; r < ey * ez; r += 16) {
-            const int iz = r / ey, iy = r - iz * ey;
-            const int y = wrapn(by0 + iy, B.ny);
-            const int z = zper ? wrapn(bz0 + iz, B.nz) : bz0 + iz;
-            for (int ix = tid & 15; ix < ex; ix += 16) {
-                int x = x0w + ix;
-                while (x >= B.nx) x -= B.nx;
-                const int64_t g = gidx(x, y, z);
-                const int c = r * ex + ix;
-                su[c] = ub[g];
-                su[MAXR + c] = ub[g + TILE_CELLS];
-                su[2 * MAXR + c] = ub[g + 2 * TILE_CELLS];
+        // the region's cells in order, four per thread and pass with all
+        // their loads issued before the first LDS store
+        const int x0w = wrapn(bx0, B.nx), y0w = wrapn(by0, B.ny), z0w = zper ? wrapn(bz0, B.nz) : bz0;
+        const int ncell = ex * ey * ez;
+        for (int c0 = 0; c0 < ncell; c0 += 4 * 256) {
+            R v[4][3];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int c = c0 + k * 256 + tid;
+                if (c < ncell) {
+                    const int r = c / ex, ix = c - r * ex;
+                    const int iz = r / ey, iy = r - iz * ey;
+                    int x = x0w + ix, y = y0w + iy, z = z0w + iz;
+                    while (x >= B.nx) x -= B.nx;
+                    while (y >= B.ny) y -= B.ny;
+                    if (zper)
+                        while (z >= B.nz) z -= B.nz;
+                    const int64_t g = gidx(x, y, z);
+                    v[k][0] = ub[g];
+                    v[k][1] = ub[g + TILE_CELLS];
+                    v[k][2] = ub[g + 2 * TILE_CELLS];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int c = c0 + k * 256 + tid;
+                if (c < ncell) {
+                    su[c] = v[k][0];
+                    su[MAXR + c] = v[k][1];
+                    su[2 * MAXR + c] = v[k][2];
+                }
             }
         }
     }
