@@ -54,3 +54,32 @@ def test_free_droplet_laplace_jump_and_zero_momentum():
     assert np.abs(mom).max() < 1e-10
     # the centre does not drift
     assert np.abs(cen - 16.0).max() < 1e-9
+
+
+@pytest.mark.slow
+def test_sessile_droplet_relaxes_to_the_spherical_cap_of_theta_eq():
+    # A sphere resting at height xi above the wall, with the wetting amplitude
+    # A of Eq. 11 for theta_eq = 90 degrees, relaxes to the spherical cap of
+    # its volume: h / R0 = (1 - cos t) (4 / (2 - 3 cos t + cos^3 t))^(1/3)
+    # (1.2599 at 90 degrees, R0 the equal-volume sphere radius) and apparent
+    # angle 2 atan(h / r_c) = theta_eq.  The film below the droplet keeps the
+    # shape slightly above the ideal cap (the paper's own run sits 3.4 % above
+    # it at xi / R0 = 0.05); 5 % on h / R0 and 5 degrees on the angle.  xi
+    # here is one lattice unit (xi / R0 = 0.1): at xi below one cell the
+    # interaction is not resolved by the 4-cell delta function and the
+    # apparent angle stays far above theta_eq.
+    from iblb_inputs import mesh
+    from iblb_inputs.configs import Box, Droplet, Workload
+    R, xi, theta = 10.0, 1.0, math.radians(90.0)
+    v, t = mesh.sphere_above_wall(4, R, 20.0, 20.0, xi)
+    wl = Workload("cap-equilibrium", [Box(40, 40, 28, tau=1.0)],
+                  [Droplet(0, v, t, sigma=0.01, theta_eq=theta, xi=xi, k_vol=2 * 0.01 / R)])
+    sim = oracle.OracleSim(wl)
+    sim.step(8000)
+    d = sim.observables()[0][0]
+    R0 = (3 * d["volume"] / (4 * math.pi)) ** (1 / 3)
+    c = math.cos(theta)
+    ideal = (1 - c) * (4 / (2 - 3 * c + c ** 3)) ** (1 / 3)
+    assert abs(d["height"] / R0 / ideal - 1.0) < 0.05, d["height"] / R0
+    theta_app = 2 * math.atan(d["height"] / d["contact_radius"])
+    assert abs(math.degrees(theta_app - theta)) < 5.0, math.degrees(theta_app)
