@@ -1,9 +1,11 @@
-"""Whole-step pins of the oracle: conservation laws and the Laplace pressure
+"""Whole-step pins of the oracle: conservation laws, the Laplace pressure
 jump of a free droplet (paper Sec. 2 and Fig. 1, pressure in units of the
-Laplace pressure).  CPU only."""
+Laplace pressure) and the equilibrium spherical cap of a sessile droplet
+(Eq. 11 and the steady heights of Sec. 3).  CPU only."""
 import math
 
 import numpy as np
+import pytest
 
 import oracle
 from iblb_inputs import configs
