@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
 // going to a wave-private LDS list in ascending order.  Either way the
 // region descriptors and partial values of GATHER_BATCH blocks load side by
 // side.
-constexpr int GATHER_GROUP = 4;
+constexpr int GATHER_GROUP = SCAN_GROUP / 64;
 constexpr int GATHER_BATCH = 4;
 
 template <typename R>
@@ -217,7 +217,8 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
     // the recorded candidates: count, flag and the MAXC slots (lane k holds
     // slot k) in one round trip
     const int ncand = ((const IBLB_CONST int32_t *)P.tncand)[(int64_t)slot * P.total_tiles + gt];
-    const bool scan = ((const IBLB_CONST int32_t *)P.scan_all)[slot * P.n_boxes + box] != 0;
+    const bool scan = !box_records(b0, b1) ||
+                      ((const IBLB_CONST int32_t *)P.scan_all)[slot * P.n_boxes + box] != 0;
     int mine = lane < MAXC ? P.tcand[(int64_t)gt * MAXC + lane] : INT_MAX;
     if (!scan && ncand <= MAXC) {
         mine = lane < ncand ? mine : INT_MAX;

@@ -41,7 +41,14 @@ static_assert(TREC == 5 * 4, "triangle record = five four-vectors");
 constexpr int K1_MAX_THREADS = 256; // launch bound of the bulk stream-collide kernel
 constexpr int MAXP = 2048;          // cells of a node block's partial-spread region
 constexpr int BREG = 8;
-constexpr int MAXC = 16;           // node blocks recorded per band tile (more: the gather scans)             // ints per block region descriptor
+constexpr int MAXC = 16;           // node blocks recorded per band tile (more: the gather scans)
+constexpr int SCAN_GROUP = 256;    // boxes with at most this many node blocks: the gather scans them all
+
+// Whether the node pass records, per band tile, the blocks covering it (a
+// box whose blocks one scan pass of the gather covers needs no records).
+__host__ __device__ inline bool box_records(int blk_begin, int blk_end) {
+    return blk_end - blk_begin > SCAN_GROUP;
+}             // ints per block region descriptor
 
 // Velocity set in the library's order: 0 = rest, i and i+9 opposite (i=1..9).
 __host__ __device__ constexpr int cx_of(int i) {

@@ -127,6 +127,7 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
         // every constant of the droplet and its box is read here, before the
         // first store (a scalar load behind vector stores waits for them)
         const int nx = B.nx, ny = B.ny, nz = B.nz, tnx = B.tnx, tny = B.tny, tile_base = B.tile_base;
+        const bool records = box_records(B.blk_begin, B.blk_end);
         const bool zper = B.zbc == 1;
         IBLB_GLOBAL int32_t *const stamp = (IBLB_GLOBAL int32_t *)B.stamp;
         const int node_off = D.node_off, n_nodes = D.n_nodes, n_exp = D.n_exp, m_exp = D.m_exp;
@@ -276,7 +277,7 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
         // from an integer counter; the gather sorts the ids, so the order of
         // the records does not matter); a block whose box spans more than 64
         // cells on an axis, or a periodic axis whole, makes its box's gather scan
-        {
+        if (mode == 0 && records) {
             const int slot = ctr & 1;
             const int lo3[3] = {bl[0], bl[1], zl}, hi3[3] = {bh[0], bh[1], zh};
             int ntl[3];
