@@ -36,6 +36,7 @@ class Box:
     rho0: float = 1.0
     zbc: int = Z_WALLS
     body_force: tuple = (0.0, 0.0, 0.0)
+    tau_in: float = 0.0        # relaxation time inside droplets (0: tau everywhere)
 
     @property
     def cells(self) -> int:

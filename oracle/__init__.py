@@ -55,7 +55,8 @@ def _declare(L):
     L.orc_feq.argtypes = [_d, _dp, _dp]
     L.orc_guo.argtypes = [_d, _dp, _dp, _dp]
     L.orc_moments.argtypes = [_dp, _dp, _vp, _dp]
-    L.orc_lb_step.argtypes = [_i, _i, _i, _i, _d, _dp, _vp, _dp, _dp, _dp, _vp, _vp]
+    L.orc_lb_step.argtypes = [_i, _i, _i, _i, _d, _dp, _vp, _dp, _vp, _d, _dp, _dp, _vp, _vp]
+    L.orc_inside.argtypes = [_i, _i, _i, _i, _ip, _dp, _bp]
     L.orc_mass.argtypes = [_C.c_size_t, _dp]
     L.orc_mass.restype = _d
     L.orc_max_u.argtypes = [_C.c_size_t, _dp]
@@ -127,9 +128,10 @@ def peskin(r):
 
 
 def lb_step(f, tau, zbc=0, F=None, g=(0.0, 0.0, 0.0), scratch=None, want_moments=True,
-            out=None, rho=None, u=None):
+            out=None, rho=None, u=None, inside=None, tau_in=0.0):
     """One LB step.  f: (19,nz,ny,nx).  Returns (f_new, rho, u); `scratch`,
-    `out`, `rho` and `u` may be passed in to reuse buffers."""
+    `out`, `rho` and `u` may be passed in to reuse buffers.  `inside`
+    (uint8 (nz,ny,nx)) marks the cells that relax with tau_in."""
     f = _f64(f)
     _, nz, ny, nx = f.shape
     fs = scratch if scratch is not None else _np.empty_like(f)
@@ -140,9 +142,11 @@ def lb_step(f, tau, zbc=0, F=None, g=(0.0, 0.0, 0.0), scratch=None, want_moments
     else:
         rho = u = None
     Fk = None if F is None else _f64(F)  # kept alive for the call
+    ins = None if inside is None else _np.ascontiguousarray(inside, dtype=_np.uint8)
     lib().orc_lb_step(nx, ny, nz, int(zbc), float(tau), f,
                       Fk.ctypes.data_as(_vp) if Fk is not None else None,
-                      _f64(g), fs, fn,
+                      _f64(g), ins.ctypes.data_as(_vp) if ins is not None else None, float(tau_in),
+                      fs, fn,
                       rho.ctypes.data_as(_vp) if rho is not None else None,
                       u.ctypes.data_as(_vp) if u is not None else None)
     return fn, rho, u
@@ -227,6 +231,17 @@ def base_cells(q, nx, ny):
     b = _np.zeros((len(q), 3), _np.int32)
     lib().orc_base_cells(len(q), _f64(q), nx, ny, b)
     return b
+
+
+def inside(shape, tris, q):
+    """uint8 (nz,ny,nx): 1 for cells whose centre the closed mesh(es) enclose
+    (parity of the crossings of the vertical ray below the centre, exact
+    integer predicates)."""
+    nz, ny, nx = shape
+    tris = _np.ascontiguousarray(tris, dtype=_np.int32)
+    out = _np.zeros((nz, ny, nx), _np.uint8)
+    lib().orc_inside(nx, ny, nz, len(tris), tris, _f64(q), out)
+    return out
 
 
 def touched_tiles(q, shape, zbc, tile=(4, 4, 4)):

@@ -146,10 +146,9 @@ static inline size_t cidx(int i, int j, int k, int nx, int ny) {
  * reading taken here.
  */
 void orc_lb_step(int nx, int ny, int nz, int zbc, double tau, const double *f,
-                 const double *F, const double *g, double *fs, double *fnew,
-                 double *rho_out, double *u_out) {
+                 const double *F, const double *g, const uint8_t *inside, double tau_in,
+                 double *fs, double *fnew, double *rho_out, double *u_out) {
     const size_t cells = (size_t)nx * ny * nz;
-    const double omega = 1.0 / tau;
     int opp[Q];
     for (int i = 0; i < Q; ++i) opp[i] = opposite_of(i);
 
@@ -161,11 +160,14 @@ void orc_lb_step(int nx, int ny, int nz, int zbc, double tau, const double *f,
                 double fc[Q], feq[Q], S[Q], Fx[3], rho, u[3];
                 for (int q = 0; q < Q; ++q) fc[q] = f[q * cells + x];
                 for (int a = 0; a < 3; ++a) Fx[a] = g[a] + (F ? F[a * cells + x] : 0.0);
+                /* relaxation time of the cell: tau_in inside a droplet (Sec. 2,
+                   below Eq. 13), tau elsewhere */
+                const double tc = (inside && inside[x]) ? tau_in : tau;
                 moments_cell(fc, Fx, &rho, u);
                 feq_cell(rho, u, feq);
-                guo_cell(tau, u, Fx, S);
+                guo_cell(tc, u, Fx, S);
                 for (int q = 0; q < Q; ++q)
-                    fs[q * cells + x] = fc[q] - (fc[q] - feq[q]) * omega + S[q];
+                    fs[q * cells + x] = fc[q] - (fc[q] - feq[q]) / tc + S[q];
                 if (rho_out) rho_out[x] = rho;
                 if (u_out)
                     for (int a = 0; a < 3; ++a) u_out[a * cells + x] = u[a];
@@ -185,6 +187,86 @@ void orc_lb_step(int nx, int ny, int nz, int zbc, double tau, const double *f,
                                         wrap1(ks, nz), nx, ny);
                         fnew[q * cells + x] = fs[q * cells + s];
                     }
+                }
+            }
+}
+
+/*
+ * Inside / outside of closed droplet meshes (Sec. 2, below Eq. 13: fluid
+ * nodes inside the droplet relax with tau_in, found by ray tracing).
+ *
+ * A cell (i, j, k) is inside when the vertical ray from its centre
+ * (i + 1/2, j + 1/2, k + 1/2) down to z = -inf crosses the mesh an odd
+ * number of times.  The decisions are exact: every coordinate is first put
+ * on the integer grid Q(v) = round(v * 2^18) (half away from zero), so the
+ * cell centre is (i * 2^18 + 2^17, ...), and all predicates are evaluated
+ * in 128-bit integers.
+ *   - The vertical line through p crosses triangle (a, b, c) when p lies in
+ *     its xy projection.  Edge function e_uv(p) = (v_x - u_x)(p_y - u_y) -
+ *     (v_y - u_y)(p_x - u_x); p is in the triangle when the three signs
+ *     agree.  A zero is resolved as if p were moved by (eps, eps^2): its sign
+ *     is that of -(v_y - u_y), or of (v_x - u_x) when v_y = u_y (simulation
+ *     of simplicity), so that a point on an edge or vertex is counted by the
+ *     same number of triangles, modulo 2, as a point next to it.  A triangle
+ *     whose projection has no area is never crossed.
+ *   - The crossing lies below the centre when z* <= z_c, with z* = N / D,
+ *     D = e_ab + e_bc + e_ca, N = e_bc a_z + e_ca b_z + e_ab c_z
+ *     (barycentric interpolation at p), decided as sign(D) (z_c D - N) >= 0.
+ * x and y are periodic: the column is taken at the image of the cell centre
+ * nearest to the triangle (droplets are smaller than half the box).
+ * The parity runs over all triangles given, so several disjoint closed
+ * meshes in one box may be passed together.
+ */
+typedef __int128 i128;
+#define QSCALE 262144.0 /* 2^18 */
+
+static inline int64_t qgrid(double v) { return (int64_t)llround(v * QSCALE); }
+
+static inline int sos_sign(i128 e, int64_t dx, int64_t dy) {
+    if (e > 0) return 1;
+    if (e < 0) return -1;
+    if (dy != 0) return dy > 0 ? -1 : 1; /* sign of -(v_y - u_y) */
+    if (dx != 0) return dx > 0 ? 1 : -1;
+    return 0;
+}
+
+static inline i128 edge_fn(int64_t ux, int64_t uy, int64_t vx, int64_t vy, int64_t px, int64_t py) {
+    return (i128)(vx - ux) * (py - uy) - (i128)(vy - uy) * (px - ux);
+}
+
+void orc_inside(int nx, int ny, int nz, int n_tris, const int32_t *tris, const double *q,
+                uint8_t *inside) {
+    const size_t cells = (size_t)nx * ny * nz;
+    memset(inside, 0, cells);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            for (int t = 0; t < n_tris; ++t) {
+                const double *A = q + 3 * (size_t)tris[3 * t], *B = q + 3 * (size_t)tris[3 * t + 1],
+                             *C = q + 3 * (size_t)tris[3 * t + 2];
+                /* image of the column nearest to the triangle */
+                const double cx = (A[0] + B[0] + C[0]) / 3.0, cy = (A[1] + B[1] + C[1]) / 3.0;
+                const double mx = floor((cx - (i + 0.5)) / nx + 0.5), my = floor((cy - (j + 0.5)) / ny + 0.5);
+                const int64_t px = (int64_t)(i + (int64_t)mx * nx) * 262144 + 131072;
+                const int64_t py = (int64_t)(j + (int64_t)my * ny) * 262144 + 131072;
+                const int64_t ax = qgrid(A[0]), ay = qgrid(A[1]), az = qgrid(A[2]);
+                const int64_t bx = qgrid(B[0]), by = qgrid(B[1]), bz = qgrid(B[2]);
+                const int64_t kx = qgrid(C[0]), ky = qgrid(C[1]), kz = qgrid(C[2]);
+                const i128 eab = edge_fn(ax, ay, bx, by, px, py);
+                const i128 ebc = edge_fn(bx, by, kx, ky, px, py);
+                const i128 eca = edge_fn(kx, ky, ax, ay, px, py);
+                const int s1 = sos_sign(eab, bx - ax, by - ay);
+                const int s2 = sos_sign(ebc, kx - bx, ky - by);
+                const int s3 = sos_sign(eca, ax - kx, ay - ky);
+                if (s1 == 0 || s1 != s2 || s2 != s3) continue;
+                const i128 D = eab + ebc + eca;
+                if (D == 0) continue;
+                const i128 N = ebc * az + eca * bz + eab * kz;
+                for (int k = 0; k < nz; ++k) {
+                    const i128 zc = (i128)k * 262144 + 131072;
+                    const i128 d = zc * D - N;
+                    if ((D > 0 && d >= 0) || (D < 0 && d <= 0))
+                        inside[cidx(i, j, k, nx, ny)] ^= 1;
                 }
             }
 }

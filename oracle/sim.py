@@ -4,7 +4,9 @@ One step t -> t+1, in the order the paper's coupling implies (Sec. 2):
   1. nodal forces phi_j at the current node positions q^t     (Eqs. 9-11)
   2. spreading of phi onto the lattice, F^t                    (Eq. 8)
   3. moments with the half-force correction, BGK collision with
-     the Guo source, streaming with halfway bounce-back         (Eqs. 1-6)
+     the Guo source (relaxation time tau_in inside the droplets,
+     tau outside, when the box sets tau_in), streaming with
+     halfway bounce-back                                         (Eqs. 1-6)
   4. interpolation of u^t (the velocity of step 3) at q^t      (Eq. 7)
   5. forward Euler advection q^{t+1} = q^t + U                 (Sec. 2)
 """
@@ -12,7 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (interp, lattice, lb_step, mass, max_u, mesh_observables, node_forces,
+from . import (inside, interp, lattice, lb_step, mass, max_u, mesh_observables, node_forces,
                spread, volume, wetting_A)
 
 
@@ -49,6 +51,17 @@ class OracleSim:
         self.below_wall += out["below_wall"]
         return out["phi"]
 
+    def inside_mask(self, bi):
+        """Cells of box bi inside one of its droplets (at the current q)."""
+        b = self.boxes[bi]
+        ds = [i for i, d in enumerate(self.drops) if d.box == bi]
+        tris, qs, off = [], [], 0
+        for di in ds:
+            tris.append(np.asarray(self.drops[di].tris, dtype=np.int32) + off)
+            qs.append(self.q[di])
+            off += len(self.q[di])
+        return inside((b.nz, b.ny, b.nx), np.concatenate(tris), np.concatenate(qs))
+
     def step(self, n: int = 1):
         for _ in range(n):
             for bi, b in enumerate(self.boxes):
@@ -59,8 +72,13 @@ class OracleSim:
                     phis[di] = self.forces(di)
                 for di in ds:
                     spread((b.nz, b.ny, b.nx), b.zbc, self.q[di], phis[di], F)
+                mask = None
+                tau_in = getattr(b, "tau_in", 0.0)
+                if tau_in > 0.0 and ds:
+                    mask = self.inside_mask(bi)
                 fn, rho, u = lb_step(self.f[bi], b.tau, b.zbc, F, b.body_force,
-                                     scratch=self._scratch[bi], out=self._spare[bi])
+                                     scratch=self._scratch[bi], out=self._spare[bi],
+                                     inside=mask, tau_in=tau_in)
                 self._spare[bi] = self.f[bi]
                 for di in ds:
                     U = interp(u, b.zbc, self.q[di])
