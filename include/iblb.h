@@ -70,7 +70,11 @@ enum {
     IBLB_BIT_RHO = 1u,        /* a density was non-finite or <= 0         */
     IBLB_BIT_MACH = 2u,       /* |u| exceeded the lattice sound speed     */
     IBLB_BIT_WALL = 4u,       /* a node reached d <= 0 (Pi is singular)   */
-    IBLB_BIT_JUMP = 8u        /* a node moved more than 1 lu in one step  */
+    IBLB_BIT_JUMP = 8u,       /* a node moved more than 1 lu in one step  */
+    IBLB_BIT_BAND = 16u       /* with tau_in: a cell went inside or outside
+                                 away from every node's stencil (triangles
+                                 too large for the mesh's node spacing);
+                                 its relaxation time lagged one step      */
 };
 
 typedef struct {
@@ -83,6 +87,17 @@ typedef struct {
                            mu = rho c_s^2 (tau - 1/2))                         */
     double rho0;        /* initial (and reference) density, > 0               */
     double body_force[3]; /* uniform force density added to every cell's F   */
+    double tau_in;      /* relaxation time of the cells inside the box's
+                           droplets, > 1/2, or 0 for tau everywhere.  Inside
+                           means: the vertical ray below the cell centre
+                           crosses the closed meshes an odd number of times
+                           (Sec. 2, below Eq. 13: ray tracing assigns tau_in
+                           and tau_out; viscosity ratio (tau_in - 1/2) /
+                           (tau - 1/2)).  Decided exactly on node positions
+                           rounded to multiples of 2^-18, a point on the
+                           surface resolved as if moved by (+e, +e^2) in x, y
+                           and a crossing at the centre's height counting as
+                           below it.  Droplets of one box must not overlap. */
 } iblb_box;
 
 typedef struct {
@@ -191,6 +206,14 @@ iblb_status iblb_interpolate(struct iblb_ctx *ctx, int32_t d, const double *u_in
                              double *U_out);
 iblb_status iblb_read_bins(struct iblb_ctx *ctx, int32_t d, int32_t *base_out);
 iblb_status iblb_read_csr(struct iblb_ctx *ctx, int32_t d, int32_t *offsets, int32_t *entries);
+
+/* Cells of box b inside its droplets at the current node positions: 1 where
+ * the vertical ray below the cell centre crosses the closed meshes an odd
+ * number of times (exact predicates; the tie rule and the periodic images
+ * are those of the tau_in field of iblb_box), else 0; [nz][ny][nx].  Only
+ * for a box with tau_in > 0 (else IBLB_E_INVAL).  Does not advance time.
+ * Synchronising. */
+iblb_status iblb_read_inside(struct iblb_ctx *ctx, int32_t b, uint8_t *inside_out);
 
 /* Launch configuration of the fused stream-collide kernel:
  *   threads_x         threads along x per row, a multiple of 32;

@@ -17,20 +17,21 @@ IBLB_E_INVAL, IBLB_E_MESH, IBLB_E_DEVICE, IBLB_E_WORKSPACE, IBLB_E_UNSTABLE, IBL
 IBLB_F64, IBLB_F32, IBLB_F16DEV, IBLB_BF16DEV = 0, 1, 2, 3
 IBLB_Z_WALLS, IBLB_Z_PERIODIC = 0, 1
 IBLB_FLAG_GRAPH, IBLB_FLAG_AUTOTUNE, IBLB_FLAG_FULL_U = 1, 2, 4
-IBLB_BIT_RHO, IBLB_BIT_MACH, IBLB_BIT_WALL, IBLB_BIT_JUMP = 1, 2, 4, 8
+IBLB_BIT_RHO, IBLB_BIT_MACH, IBLB_BIT_WALL, IBLB_BIT_JUMP, IBLB_BIT_BAND = 1, 2, 4, 8, 16
 
 EXPORTS = (
     "iblb_velocity_set", "iblb_workspace_size", "iblb_init", "iblb_step", "iblb_observables",
     "iblb_read_state", "iblb_write_state", "iblb_read_nodes", "iblb_write_nodes",
     "iblb_compute_forces", "iblb_compute_spread", "iblb_interpolate", "iblb_read_bins",
-    "iblb_read_csr", "iblb_set_launch", "iblb_get_launch", "iblb_band_tile", "iblb_time_stream_collide",
+    "iblb_read_csr", "iblb_read_inside", "iblb_set_launch", "iblb_get_launch", "iblb_band_tile", "iblb_time_stream_collide",
     "iblb_destroy", "iblb_last_error",
 )
 
 
 class iblb_box(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("zbc", C.c_int32),
-                ("tau", C.c_double), ("rho0", C.c_double), ("body_force", C.c_double * 3)]
+                ("tau", C.c_double), ("rho0", C.c_double), ("body_force", C.c_double * 3),
+                ("tau_in", C.c_double)]
 
 
 class iblb_droplet(C.Structure):
@@ -91,6 +92,7 @@ def load():
     L.iblb_interpolate.argtypes = [vp, i32, dp, dp]
     L.iblb_read_bins.argtypes = [vp, i32, ip]
     L.iblb_read_csr.argtypes = [vp, i32, ip, ip]
+    L.iblb_read_inside.argtypes = [vp, i32, C.POINTER(C.c_uint8)]
     L.iblb_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
     L.iblb_get_launch.argtypes = [vp, ip, ip, ip, ip, ip]
     L.iblb_band_tile.argtypes = [ip]
@@ -141,7 +143,8 @@ def make_config(workload, storage=None, flags=0, dev_scale=None):
     boxes = (iblb_box * nb)()
     for k, b in enumerate(workload.boxes):
         boxes[k] = iblb_box(b.nx, b.ny, b.nz, b.zbc, b.tau, b.rho0,
-                            (C.c_double * 3)(*[float(v) for v in b.body_force]))
+                            (C.c_double * 3)(*[float(v) for v in b.body_force]),
+                            float(getattr(b, "tau_in", 0.0)))
     drops = (iblb_droplet * max(nd, 1))()
     keep = [boxes, drops]
     for k, d in enumerate(workload.droplets):
@@ -277,6 +280,13 @@ class Simulation:
         ent = np.empty(3 * len(dr.tris), np.int32)
         self._chk(load().iblb_read_csr(self.ctx, d, _iptr(off), _iptr(ent)))
         return off, ent
+
+    def read_inside(self, b=0):
+        """Inside bits of box b at the current node positions, uint8 [nz][ny][nx]."""
+        bx = self.wl.boxes[b]
+        m = np.empty((bx.nz, bx.ny, bx.nx), np.uint8)
+        self._chk(load().iblb_read_inside(self.ctx, b, m.ctypes.data_as(C.POINTER(C.c_uint8))))
+        return m
 
     def set_launch(self, threads_x, rows, cells_per_thread=1, streaming_stores=0, max_workgroups=0):
         self._chk(load().iblb_set_launch(self.ctx, int(threads_x), int(rows), int(cells_per_thread),

@@ -42,6 +42,8 @@ struct BoxHost {
     int64_t plane = 0;
     int blk_begin = 0, blk_end = 0;
     size_t off_f[2] = {0, 0}, off_stamp = 0, off_F = 0, off_u = 0, off_ufull = 0;
+    size_t off_mask[2] = {0, 0};
+    int nzw = 0;  // 64-bit mask words per column (boxes with tau_in)
 };
 
 struct Plan {
@@ -170,6 +172,8 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
         if (B.zbc != IBLB_Z_WALLS && B.zbc != IBLB_Z_PERIODIC)
             return fail(err, IBLB_E_INVAL, nm + ": unknown z boundary");
         if (!(B.tau > 0.5) || !finite(B.tau)) return fail(err, IBLB_E_INVAL, nm + ": tau must exceed 1/2");
+        if (!(B.tau_in == 0.0 || (B.tau_in > 0.5 && finite(B.tau_in))))
+            return fail(err, IBLB_E_INVAL, nm + ": tau_in must be 0 or exceed 1/2");
         if (!(B.rho0 > 0) || !finite(B.rho0)) return fail(err, IBLB_E_INVAL, nm + ": rho0 must be > 0");
         for (int a = 0; a < 3; ++a)
             if (!finite(B.body_force[a])) return fail(err, IBLB_E_INVAL, nm + ": body force not finite");
@@ -289,6 +293,10 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
         H.off_F = take((size_t)H.n_tiles * 3 * TILE_CELLS * p.real);
         H.off_u = take((size_t)H.n_tiles * 3 * TILE_CELLS * p.real);
         if (p.flags & IBLB_FLAG_FULL_U) H.off_ufull = take((size_t)3 * H.plane * p.real);
+        if (H.b.tau_in > 0.0) {
+            H.nzw = (H.b.nz + 63) / 64;
+            for (int k = 0; k < 2; ++k) H.off_mask[k] = take((size_t)H.nzw * H.b.ny * H.b.nx * 8);
+        }
     }
     p.off_boxes = take(sizeof(BoxDev) * p.boxes.size());
     p.off_drops = take(sizeof(DropDev) * std::max<size_t>(p.drops.size(), 1));
@@ -382,6 +390,15 @@ iblb_status upload_rows(iblb_ctx *c) {
     return IBLB_OK;
 }
 
+// Inside bits (boxes with tau_in) of the current node positions into mask
+// set `slot`: cleared by a kernel, then toggled by the triangles.
+iblb_status compute_masks(iblb_ctx *c, int slot, hipStream_t s) {
+    if (!c->P.contrast) return IBLB_OK;
+    HIPCHK(c, launch_mask_clear(c->P, slot, s));
+    HIPCHK(c, launch_inside(c->P, is_f64(c), slot, s));
+    return IBLB_OK;
+}
+
 // One time step on stream s.  The bulk stream-collide (every cell, body
 // force only) runs on s while the mesh chain runs on the second stream:
 // [advection of the previous step] -> triangle records -> node pass (forces,
@@ -401,8 +418,14 @@ iblb_status enqueue_step(iblb_ctx *c, hipStream_t s, int parity, bool advect_fir
     HIPCHK(c, hipEventRecord(c->ev_fork, s));
     HIPCHK(c, hipStreamWaitEvent(c->ib, c->ev_fork, 0));
     if (advect_first) HIPCHK(c, launch_interp(c->P, f64, 0, nullptr, c->ib));
+    {
+        // this step's inside bits (the bulk kernel reads the other set)
+        const iblb_status st = compute_masks(c, parity, c->ib);
+        if (st != IBLB_OK) return st;
+    }
     HIPCHK(c, launch_tri(c->P, f64, c->ib));
     HIPCHK(c, launch_node(c->P, f64, 0, c->ib));
+    HIPCHK(c, launch_mask_check(c->P, parity, c->ib));
     HIPCHK(c, hipEventRecord(c->ev_join, c->ib));
     HIPCHK(c, launch_bulk(c->P, c->plan.storage, parity, full_u, scale, c->L, s));
     HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
@@ -500,6 +523,10 @@ iblb_status reset_state(iblb_ctx *c) {
                                  c->stream));
     }
     HIPCHK(c, hipMemsetAsync(c->P.status, 0, 4, c->stream));
+    for (int k = 0; k < 2; ++k) {
+        const iblb_status st = compute_masks(c, k, c->stream);
+        if (st != IBLB_OK) return st;
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->pending) {
         // the dropped advection would have started a new epoch: start it here,
@@ -786,6 +813,15 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
         D.omega = 1.0 / H.b.tau;
         D.guo = 1.0 - 1.0 / (2.0 * H.b.tau);
         D.cells_rho0 = (double)H.b.nx * H.b.ny * H.b.nz * H.b.rho0;
+        D.contrast = H.b.tau_in > 0.0 ? 1 : 0;
+        D.nzw = H.nzw;
+        D.omega_in = D.contrast ? 1.0 / H.b.tau_in : D.omega;
+        D.guo_in = D.contrast ? 1.0 - 1.0 / (2.0 * H.b.tau_in) : D.guo;
+        for (int k = 0; k < 2; ++k) D.mask[k] = D.contrast ? (uint64_t *)at(H.off_mask[k]) : nullptr;
+        if (D.contrast) {
+            P.contrast = 1;
+            P.mask_words = std::max(P.mask_words, (int32_t)((int64_t)D.nzw * D.ny * D.nx));
+        }
         for (int k = 0; k < (int)round_up((size_t)H.n_tiles, TILE_CELLS) / TILE_CELLS; ++k)
             tchunk[H.tile_base / TILE_CELLS + k] = (int32_t)b;
     }
@@ -886,6 +922,13 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     // reference volumes V0 from the initial mesh (same FP64 sum as the penalty)
     HIPCHK(c, launch_tri(P, is_f64(c), c->stream));
     HIPCHK(c, launch_set_v0(P, is_f64(c), c->stream));
+    // inside bits of the initial positions in both sets
+    for (int k = 0; k < 2 && st == IBLB_OK; ++k) st = compute_masks(c, k, c->stream);
+    if (st != IBLB_OK) {
+        g_last_error = c->err;
+        iblb_destroy(c);
+        return st;
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
 
     // default launch shape of the stream-collide kernel
@@ -1158,6 +1201,10 @@ iblb_status iblb_write_nodes(iblb_ctx *c, int32_t d, const double *nodes_in) {
         }
     HIPCHK(c, hipMemcpy(c->P.qh, qh.data(), qh.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->P.ql, ql.data(), ql.size(), hipMemcpyHostToDevice));
+    // the next step's bulk collision reads the other set of inside bits
+    const iblb_status st = compute_masks(c, c->parity ^ 1, c->stream);
+    if (st != IBLB_OK) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return IBLB_OK;
 }
 
@@ -1286,6 +1333,32 @@ iblb_status iblb_read_bins(iblb_ctx *c, int32_t d, int32_t *base_out) {
         base_out[u + 1] = wrap(base[(size_t)N + H.node_off + k], B.ny);
         base_out[u + 2] = base[2 * (size_t)N + H.node_off + k];
     }
+    return IBLB_OK;
+}
+
+iblb_status iblb_read_inside(iblb_ctx *c, int32_t b, uint8_t *inside_out) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (b < 0 || b >= c->P.n_boxes || !inside_out) return set_err(c, IBLB_E_INVAL, "bad box or output");
+    const BoxHost &H = c->plan.boxes[b];
+    if (!(H.b.tau_in > 0.0)) return set_err(c, IBLB_E_INVAL, "box has no tau_in");
+    {
+        iblb_status fst = flush(c);
+        if (fst != IBLB_OK) return fst;
+    }
+    // the next step recomputes this set before any kernel reads it
+    {
+        iblb_status st = compute_masks(c, c->parity, c->stream);
+        if (st != IBLB_OK) return st;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz;
+    std::vector<uint64_t> m((size_t)H.nzw * ny * nx);
+    HIPCHK(c, hipMemcpy(m.data(), c->ws + H.off_mask[c->parity], m.size() * 8, hipMemcpyDeviceToHost));
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x)
+                inside_out[((size_t)z * ny + y) * nx + x] =
+                    (uint8_t)((m[((size_t)(z >> 6) * ny + y) * nx + x] >> (z & 63)) & 1u);
     return IBLB_OK;
 }
 

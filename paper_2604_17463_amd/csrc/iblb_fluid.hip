@@ -37,6 +37,9 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
         const IBLB_GLOBAL char *__restrict__ src = (const IBLB_GLOBAL char *)B->f[parity];
         IBLB_GLOBAL char *__restrict__ dst = (IBLB_GLOBAL char *)B->f[parity ^ 1];
         const R omega = (R)B->omega, guo = (R)B->guo, rho0 = (R)B->rho0;
+        const R omega_in = (R)B->omega_in, guo_in = (R)B->guo_in;
+        const bool contrast = B->contrast != 0;
+        const IBLB_GLOBAL uint64_t *mprev = (const IBLB_GLOBAL uint64_t *)B->mask[parity ^ 1];
         const R gx = (R)B->g[0], gy = (R)B->g[1], gz = (R)B->g[2];
         IBLB_GLOBAL R *__restrict__ uf = (IBLB_GLOBAL R *)B->ufull;
         const uint64_t plane = (uint64_t)B->plane;
@@ -49,11 +52,14 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
         for (; r < rg.r1; r += BY * CPT) {
             RowAddr ra[CPT];
             bool on[CPT];
+            int ryk[CPT], rzk[CPT];
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
                 on[k] = r + k * BY < rg.r1;
                 const int ry = UROW ? __builtin_amdgcn_readfirstlane(y) : y;
                 const int rz = UROW ? __builtin_amdgcn_readfirstlane(z) : z;
+                ryk[k] = ry;
+                rzk[k] = rz;
                 ra[k] = row_addr(ry, rz, ny, nz, sx, zper, EB);
                 y += BY;
                 while (y >= ny) {
@@ -77,7 +83,18 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                     if (!on[k]) continue;
                     R out[Q], u[3], rho;
                     const uint32_t own = ra[k].ro[1][1] + xo.c;
-                    collide<ST>(g[k], gx, gy, gz, rho0, omega, guo, scale, inv, out, u, rho);
+                    R om = omega, gu = guo;
+                    if (contrast) {
+                        // inside bits of the previous step: a cell whose bit
+                        // changes since then lies in the band, which the band
+                        // kernel recomputes with this step's bits
+                        const uint64_t w = mprev[((int64_t)(rzk[k] >> 6) * ny + ryk[k]) * nx + x];
+                        if ((w >> (rzk[k] & 63)) & 1ull) {
+                            om = omega_in;
+                            gu = guo_in;
+                        }
+                    }
+                    collide<ST>(g[k], gx, gy, gz, rho0, om, gu, scale, inv, out, u, rho);
                     if constexpr (BUF)
                         store_buf<ST, NT>(rd, (uint32_t)pb, ra[k].ro[1][1], xo.c, out);
                     else
@@ -316,8 +333,16 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
         if (!inside) continue;
         R out[Q], u[3], rho;
         const uint32_t own = ra.ro[1][1] + xo.c;
-        collide<ST>(g, (R)B->g[0] + F0, (R)B->g[1] + F1, (R)B->g[2] + F2, (R)B->rho0, (R)B->omega,
-                    (R)B->guo, scale, inv, out, u, rho);
+        R om = (R)B->omega, gu = (R)B->guo;
+        if (B->contrast) {  // this step's inside bits
+            const uint64_t w = ((const IBLB_GLOBAL uint64_t *)B->mask[parity])[((int64_t)(cz >> 6) * B->ny + cy) * B->nx + cx];
+            if ((w >> (cz & 63)) & 1ull) {
+                om = (R)B->omega_in;
+                gu = (R)B->guo_in;
+            }
+        }
+        collide<ST>(g, (R)B->g[0] + F0, (R)B->g[1] + F1, (R)B->g[2] + F2, (R)B->rho0, om, gu, scale, inv,
+                    out, u, rho);
         store_buf<ST, false, true>(pop_res(B->f[parity ^ 1], pb), (uint32_t)pb, ra.ro[1][1], xo.c, out);
         IBLB_GLOBAL R *ub = (IBLB_GLOBAL R *)B->uband + (int64_t)lt * 3 * TILE_CELLS;
         ub[lane] = u[0];

@@ -76,7 +76,7 @@ __host__ __device__ constexpr double w_of(int i) {
 // base: their bytes may not exceed this.
 constexpr int64_t BUF_MAX_PLANE_GROUP = 0xFFFFFFFFll;
 
-enum : uint32_t { BIT_RHO = 1u, BIT_MACH = 2u, BIT_WALL = 4u, BIT_JUMP = 8u };
+enum : uint32_t { BIT_RHO = 1u, BIT_MACH = 2u, BIT_WALL = 4u, BIT_JUMP = 8u, BIT_BAND = 16u };
 
 struct BoxDev {
     int32_t nx, ny, nz, zbc;
@@ -92,6 +92,9 @@ struct BoxDev {
     double tau, rho0, g[3];
     double omega, guo;          // 1/tau, 1 - 1/(2 tau)
     double cells_rho0;          // nx*ny*nz*rho0
+    double omega_in, guo_in;    // the same with tau_in (cells inside droplets)
+    int32_t contrast, nzw;      // tau_in set; 64-bit words per column (ceil(nz/64))
+    uint64_t *mask[2];          // [nzw][ny][nx] inside bits, one set per step parity
 };
 
 struct DropDev {
@@ -143,6 +146,8 @@ struct DevPtrs {
     double *obs_out;            // per droplet [12], per box [2]
     int32_t Ntot, nblk, Ttot, n_chunks;
     int32_t n_rowgroups, total_tiles, obs_groups, n_cus;  // n_cus: compute units of the device
+    int32_t contrast;           // some box has tau_in set
+    int32_t mask_words;         // largest nzw*ny*nx over those boxes
 };
 
 // Launch entry points (iblb_fluid.hip, iblb_mesh.hip).
@@ -163,6 +168,9 @@ hipError_t launch_band(const DevPtrs &P, int storage, int parity, int full_u, fl
                        bool collide, hipStream_t s);
 hipError_t launch_interp(const DevPtrs &P, bool f64, int mode, double *Uout, hipStream_t s);
 hipError_t launch_epoch(const DevPtrs &P, hipStream_t s);
+hipError_t launch_inside(const DevPtrs &P, bool f64, int slot, hipStream_t s);
+hipError_t launch_mask_clear(const DevPtrs &P, int slot, hipStream_t s);
+hipError_t launch_mask_check(const DevPtrs &P, int slot, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_box_obs(const DevPtrs &P, int storage, int parity, float inv_scale,
                           hipStream_t s);

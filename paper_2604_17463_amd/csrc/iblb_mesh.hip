@@ -720,6 +720,175 @@ hipError_t launch_interp(const DevPtrs &P, bool f64, int mode, double *Uout, hip
     return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------ inside bits
+// Cells inside the droplets of boxes with tau_in (Sec. 2, below Eq. 13).  A
+// cell is inside when the vertical ray below its centre crosses the closed
+// meshes an odd number of times.  Every triangle toggles, in each column
+// whose vertical line crosses it, the bits of the cells whose centre lies at
+// or above the crossing; XOR does not depend on the order of the toggles,
+// so the result is exact and the same in every run.
+//   - Coordinates are rounded to the grid of 2^-18 lattice units (half away
+//     from zero); the cell centre (i + 1/2) is i 2^18 + 2^17 on that grid.
+//   - The line through column point p crosses the triangle when the signs
+//     of the three edge functions e_uv(p) = (v_x - u_x)(p_y - u_y) -
+//     (v_y - u_y)(p_x - u_x) agree; a zero takes the sign it would have with
+//     p moved by (+e, +e^2): that of -(v_y - u_y), else of (v_x - u_x).
+//   - With D = e_ab + e_bc + e_ca and N = e_bc a_z + e_ca b_z + e_ab c_z the
+//     crossing lies at or below the centre z_c when sign(D) (z_c D - N) >= 0.
+// Edge functions and their products are exact in 128-bit integers.
+namespace {
+constexpr int64_t QS = 1 << 18, QH = 1 << 17;
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {  // b > 0
+    return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+__device__ __forceinline__ int sos_sign(__int128 e, int64_t dx, int64_t dy) {
+    if (e > 0) return 1;
+    if (e < 0) return -1;
+    if (dy != 0) return dy > 0 ? -1 : 1;
+    if (dx != 0) return dx > 0 ? 1 : -1;
+    return 0;
+}
+__device__ __forceinline__ __int128 edge_fn(int64_t ux, int64_t uy, int64_t vx, int64_t vy, int64_t px,
+                                            int64_t py) {
+    return (__int128)(vx - ux) * (py - uy) - (__int128)(vy - uy) * (px - ux);
+}
+}  // namespace
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_inside(DevPtrs P, int slot) {
+    const TriChunk ch = P.chunks[blockIdx.x];
+    const DropDev &D = P.drops[ch.drop];
+    const BoxDev &B = P.boxes[D.box];
+    if (!B.contrast) return;
+    const int t = ch.t0 + threadIdx.x;
+    if (t >= ch.t1) return;
+    const R *qh = (const R *)P.qh, *ql = (const R *)P.ql;
+    const int N = P.Ntot, nx = B.nx, ny = B.ny, nz = B.nz, nzw = B.nzw;
+    uint64_t *mask = B.mask[slot];
+    int64_t X[3], Y[3], Z[3];
+    bool sane = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int j = P.tri[3 * t + c];
+        const double x = (double)qh[j] + (double)ql[j];
+        const double y = (double)qh[N + j] + (double)ql[N + j];
+        const double z = (double)qh[2 * N + j] + (double)ql[2 * N + j];
+        // |coordinate| < 2^20 keeps every product below in 128 bits (NaN fails too)
+        sane = sane && fabs(x) < 0x1p20 && fabs(y) < 0x1p20 && fabs(z) < 0x1p20;
+        X[c] = sane ? llround(x * (double)QS) : 0;
+        Y[c] = sane ? llround(y * (double)QS) : 0;
+        Z[c] = sane ? llround(z * (double)QS) : 0;
+    }
+    // columns whose point lies in the triangle's xy bounding box
+    const int64_t xmin = min(X[0], min(X[1], X[2])), xmax = max(X[0], max(X[1], X[2]));
+    const int64_t ymin = min(Y[0], min(Y[1], Y[2])), ymax = max(Y[0], max(Y[1], Y[2]));
+    const int64_t iu0 = -floor_div(-(xmin - QH), QS), iu1 = floor_div(xmax - QH, QS);
+    const int64_t ju0 = -floor_div(-(ymin - QH), QS), ju1 = floor_div(ymax - QH, QS);
+    // a triangle wider than the box (a blown-up mesh; the step reports the
+    // instability) is left out rather than looped over
+    if (!sane || iu1 - iu0 >= nx || ju1 - ju0 >= ny) return;
+    for (int64_t ju = ju0; ju <= ju1; ++ju)
+        for (int64_t iu = iu0; iu <= iu1; ++iu) {
+            const int64_t px = iu * QS + QH, py = ju * QS + QH;
+            const __int128 eab = edge_fn(X[0], Y[0], X[1], Y[1], px, py);
+            const __int128 ebc = edge_fn(X[1], Y[1], X[2], Y[2], px, py);
+            const __int128 eca = edge_fn(X[2], Y[2], X[0], Y[0], px, py);
+            const int s1 = sos_sign(eab, X[1] - X[0], Y[1] - Y[0]);
+            const int s2 = sos_sign(ebc, X[2] - X[1], Y[2] - Y[1]);
+            const int s3 = sos_sign(eca, X[0] - X[2], Y[0] - Y[2]);
+            if (s1 == 0 || s1 != s2 || s2 != s3) continue;
+            const __int128 Dt = eab + ebc + eca;
+            if (Dt == 0) continue;
+            const __int128 Nt = ebc * Z[0] + eca * Z[1] + eab * Z[2];
+            auto below = [&](int k) {  // crossing at or below the centre of cell k
+                const __int128 d = ((__int128)k * QS + QH) * Dt - Nt;
+                return Dt > 0 ? d >= 0 : d <= 0;
+            };
+            // first cell above the crossing: an estimate in FP64, then exact steps
+            const double ea = (double)(X[1] - X[0]) * (double)(py - Y[0]) - (double)(Y[1] - Y[0]) * (double)(px - X[0]);
+            const double eb = (double)(X[2] - X[1]) * (double)(py - Y[1]) - (double)(Y[2] - Y[1]) * (double)(px - X[1]);
+            const double ec = (double)(X[0] - X[2]) * (double)(py - Y[2]) - (double)(Y[0] - Y[2]) * (double)(px - X[2]);
+            const double zs = (eb * (double)Z[0] + ec * (double)Z[1] + ea * (double)Z[2]) / (ea + eb + ec);
+            int k0 = (int)fmin(fmax(ceil(zs / (double)QS - 0.5), 0.0), (double)nz);
+            while (k0 > 0 && below(k0 - 1)) --k0;
+            while (k0 < nz && !below(k0)) ++k0;
+            if (k0 >= nz) continue;
+            const int i = (int)(iu % nx + (iu % nx < 0 ? nx : 0));
+            const int j = (int)(ju % ny + (ju % ny < 0 ? ny : 0));
+            for (int w = k0 >> 6; w < nzw; ++w) {
+                const uint64_t bits = w == (k0 >> 6) ? (~0ull << (k0 & 63)) : ~0ull;
+                atomicXor((unsigned long long *)&mask[((int64_t)w * ny + j) * nx + i], (unsigned long long)bits);
+            }
+        }
+}
+
+// Grid (chunks, boxes): every thread walks mask words of box blockIdx.y.
+__global__ void __launch_bounds__(256) k_mask_clear(DevPtrs P, int slot) {
+    const BoxDev &B = P.boxes[blockIdx.y];
+    if (!B.contrast) return;
+    const int64_t n = (int64_t)B.nzw * B.ny * B.nx;
+    uint64_t *m = B.mask[slot];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        m[i] = 0;
+}
+
+// The bulk kernel relaxes with the previous step's inside bits and the band
+// kernel redoes the stamped tiles with this step's.  That equals using this
+// step's bits everywhere only while every cell whose bit changed lies in a
+// stamped tile; a changed cell outside them (triangles larger than the node
+// stencils) sets BIT_BAND.  Runs after this step's stamps are written.
+__global__ void __launch_bounds__(256) k_mask_check(DevPtrs P, int slot) {
+    const BoxDev &B = P.boxes[blockIdx.y];
+    if (!B.contrast) return;
+    const int nx = B.nx, ny = B.ny, nz = B.nz;
+    const int64_t n = (int64_t)B.nzw * ny * nx;
+    const uint64_t *m0 = B.mask[slot], *m1 = B.mask[slot ^ 1];
+    const int ctr = *P.ctr;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t d = m0[i] ^ m1[i];
+        if (!d) continue;
+        const int x = (int)(i % nx);
+        const int64_t r = i / nx;
+        const int y = (int)(r % ny), zw = (int)(r / ny);
+        while (d) {
+            const int z = zw * 64 + __builtin_ctzll(d);
+            d &= d - 1;
+            if (z >= nz) break;
+            if (B.stamp[band_tile(x, y, z, B.tnx, B.tny)] != ctr) bad = true;
+        }
+    }
+    if (bad) atomicOr(P.status, BIT_BAND);
+}
+
+namespace {
+dim3 mask_grid(const DevPtrs &P) {
+    const int64_t g = ((int64_t)P.mask_words + 255) / 256;
+    return dim3((unsigned)(g < 1024 ? (g > 0 ? g : 1) : 1024), (unsigned)P.n_boxes);
+}
+}  // namespace
+
+hipError_t launch_mask_clear(const DevPtrs &P, int slot, hipStream_t s) {
+    if (!P.contrast) return hipSuccess;
+    hipLaunchKernelGGL(k_mask_clear, mask_grid(P), dim3(256), 0, s, P, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_check(const DevPtrs &P, int slot, hipStream_t s) {
+    if (!P.contrast) return hipSuccess;
+    hipLaunchKernelGGL(k_mask_check, mask_grid(P), dim3(256), 0, s, P, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_inside(const DevPtrs &P, bool f64, int slot, hipStream_t s) {
+    if (P.n_chunks == 0) return hipSuccess;
+    if (f64) hipLaunchKernelGGL(k_inside<double>, dim3(P.n_chunks), dim3(TRI_CHUNK), 0, s, P, slot);
+    else hipLaunchKernelGGL(k_inside<float>, dim3(P.n_chunks), dim3(TRI_CHUNK), 0, s, P, slot);
+    return hipGetLastError();
+}
+
 hipError_t launch_epoch(const DevPtrs &P, hipStream_t s) {
     hipLaunchKernelGGL(k_epoch, dim3(1), dim3(64), 0, s, P);
     return hipGetLastError();
