@@ -14,9 +14,11 @@ namespace iblb {
 // (threads_x a multiple of 64), so the row addressing is wave-uniform and
 // lives in scalar registers.  NT: the populations are written with
 // streaming stores (they are read again only in the next step; pays off
-// once the two population buffers exceed the last-level cache).  Cells
-// next to a mesh are recomputed by the band kernel afterwards.
-template <int ST, bool UROW, bool NT, int CPT>
+// once the two population buffers exceed the last-level cache).  EXT: some
+// box has a viscosity contrast (the plain variant carries none of its
+// registers).  Cells next to a mesh are recomputed by the band kernel
+// afterwards.
+template <int ST, bool UROW, bool NT, int CPT, bool EXT>
 __global__ void __launch_bounds__(K1_MAX_THREADS)
     k_bulk(DevPtrs P, int parity, int full_u, float scale, float inv) {
     using S = Stor<ST>;
@@ -84,7 +86,7 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                     R out[Q], u[3], rho;
                     const uint32_t own = ra[k].ro[1][1] + xo.c;
                     R om = omega, gu = guo;
-                    if (contrast) {
+                    if (EXT && contrast) {
                         // inside bits of the previous step: a cell whose bit
                         // changes since then lies in the band, which the band
                         // kernel recomputes with this step's bits
@@ -445,10 +447,16 @@ __global__ void __launch_bounds__(256) k_box_obs_final(DevPtrs P, int box, int g
 template <int ST, bool UROW, bool NT>
 static void launch_bulk_c(const DevPtrs &P, int parity, int full_u, float scale, float inv, const Launch &L,
                           dim3 grid, dim3 block, hipStream_t s) {
-    if (UROW && L.cpt == 2)
-        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2>), grid, block, 0, s, P, parity, full_u, scale, inv);
-    else
-        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    if (P.contrast) {
+        if (UROW && L.cpt == 2)
+            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
+        else
+            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    } else if (UROW && L.cpt == 2) {
+        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    } else {
+        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+    }
 }
 
 template <int ST>
