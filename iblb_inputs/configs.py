@@ -37,6 +37,8 @@ class Box:
     zbc: int = Z_WALLS
     body_force: tuple = (0.0, 0.0, 0.0)
     tau_in: float = 0.0        # relaxation time inside droplets (0: tau everywhere)
+    wall_lo: tuple = (0.0, 0.0)  # (ux, uy) of the wall at z = 0
+    wall_hi: tuple = (0.0, 0.0)  # (ux, uy) of the wall at z = nz
 
     @property
     def cells(self) -> int:

@@ -55,7 +55,7 @@ def _declare(L):
     L.orc_feq.argtypes = [_d, _dp, _dp]
     L.orc_guo.argtypes = [_d, _dp, _dp, _dp]
     L.orc_moments.argtypes = [_dp, _dp, _vp, _dp]
-    L.orc_lb_step.argtypes = [_i, _i, _i, _i, _d, _dp, _vp, _dp, _vp, _d, _dp, _dp, _vp, _vp]
+    L.orc_lb_step.argtypes = [_i, _i, _i, _i, _d, _dp, _vp, _dp, _vp, _d, _vp, _d, _dp, _dp, _vp, _vp]
     L.orc_inside.argtypes = [_i, _i, _i, _i, _ip, _dp, _bp]
     L.orc_mass.argtypes = [_C.c_size_t, _dp]
     L.orc_mass.restype = _d
@@ -68,6 +68,7 @@ def _declare(L):
     L.orc_triangle_geometry.argtypes = [_i, _ip, _dp, _dp, _dp]
     L.orc_volume.argtypes = [_i, _ip, _dp]
     L.orc_volume.restype = _d
+    L.orc_volume_moments.argtypes = [_i, _ip, _dp, _dp, _dp]
     L.orc_area.argtypes = [_i, _ip, _dp]
     L.orc_area.restype = _d
     L.orc_wetting_A.argtypes = [_d, _d, _d, _i, _i]
@@ -128,10 +129,12 @@ def peskin(r):
 
 
 def lb_step(f, tau, zbc=0, F=None, g=(0.0, 0.0, 0.0), scratch=None, want_moments=True,
-            out=None, rho=None, u=None, inside=None, tau_in=0.0):
+            out=None, rho=None, u=None, inside=None, tau_in=0.0, u_wall=None, rho_wall=1.0):
     """One LB step.  f: (19,nz,ny,nx).  Returns (f_new, rho, u); `scratch`,
     `out`, `rho` and `u` may be passed in to reuse buffers.  `inside`
-    (uint8 (nz,ny,nx)) marks the cells that relax with tau_in."""
+    (uint8 (nz,ny,nx)) marks the cells that relax with tau_in.  `u_wall`:
+    ((ux, uy) of the wall at z = 0, (ux, uy) of the wall at z = nz), or None
+    for resting walls; rho_wall enters the moving-wall term."""
     f = _f64(f)
     _, nz, ny, nx = f.shape
     fs = scratch if scratch is not None else _np.empty_like(f)
@@ -143,9 +146,11 @@ def lb_step(f, tau, zbc=0, F=None, g=(0.0, 0.0, 0.0), scratch=None, want_moments
         rho = u = None
     Fk = None if F is None else _f64(F)  # kept alive for the call
     ins = None if inside is None else _np.ascontiguousarray(inside, dtype=_np.uint8)
+    uw = None if u_wall is None else _f64(_np.reshape(u_wall, 4))
     lib().orc_lb_step(nx, ny, nz, int(zbc), float(tau), f,
                       Fk.ctypes.data_as(_vp) if Fk is not None else None,
                       _f64(g), ins.ctypes.data_as(_vp) if ins is not None else None, float(tau_in),
+                      uw.ctypes.data_as(_vp) if uw is not None else None, float(rho_wall),
                       fs, fn,
                       rho.ctypes.data_as(_vp) if rho is not None else None,
                       u.ctypes.data_as(_vp) if u is not None else None)
@@ -191,6 +196,40 @@ def triangle_geometry(tris, q):
 
 def volume(tris, q):
     return lib().orc_volume(len(tris), _i32(tris), _f64(q))
+
+
+def volume_moments(tris, q, ref=(0.0, 0.0, 0.0)):
+    """(V, first moments [3], second moments [3,3]) of the enclosed volume
+    about ref."""
+    out = _np.zeros(10)
+    lib().orc_volume_moments(len(tris), _i32(tris), _f64(q), _f64(ref), out)
+    xx, yy, zz, xy, xz, yz = out[4:]
+    M2 = _np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]])
+    return out[0], out[1:4].copy(), M2
+
+
+def deformation(tris, q):
+    """Deformation index in the shear (x, z) plane (Sec. 4): the semi-axes
+    r1 >= r3 of the ellipsoid whose second moments about the centroid equal
+    the droplet's (an ellipsoid of semi-axis r along a principal direction
+    has int x^2 dV = V r^2 / 5), D = (r1 - r3) / (r1 + r3); `inclination` is
+    the angle of the r1 axis from the x axis toward z, in (-pi/2, pi/2]."""
+    q = _f64(q)
+    ref = q.mean(0)
+    V, M1, M2 = volume_moments(tris, q, ref)
+    c = M1 / V
+    C = M2 / V - _np.outer(c, c)
+    S = C[_np.ix_([0, 2], [0, 2])]
+    lam, vec = _np.linalg.eigh(S)
+    r3, r1 = _np.sqrt(5.0 * lam)
+    v = vec[:, 1]
+    ang = _np.arctan2(v[1], v[0])
+    if ang <= -_np.pi / 2:
+        ang += _np.pi
+    elif ang > _np.pi / 2:
+        ang -= _np.pi
+    return {"D": (r1 - r3) / (r1 + r3), "r1": r1, "r3": r3, "inclination": ang,
+            "centroid": c + ref}
 
 
 def area(tris, q):

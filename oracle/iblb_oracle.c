@@ -144,9 +144,16 @@ static inline size_t cidx(int i, int j, int k, int nx, int ny) {
  * (f_i(x,t+1) = f*_opp(i)(x,t)).  The paper calls the wall a flat no-slip
  * solid and does not name the lattice scheme; halfway bounce-back is the
  * reading taken here.
+ *   uwall  : NULL for resting walls, else the in-plane velocities of the
+ *            walls, {x, y} of the wall at z = 0 then of the wall at z = nz.
+ *            A wall moving with u_w adds to the reflected population the
+ *            momentum it imparts, 2 w_i rho_w (c_i . u_w) / c_s^2 with
+ *            rho_w = rho_wall (the free droplet in shear of Sec. 4 is
+ *            driven by two such walls).
  */
 void orc_lb_step(int nx, int ny, int nz, int zbc, double tau, const double *f,
                  const double *F, const double *g, const uint8_t *inside, double tau_in,
+                 const double *uwall, double rho_wall,
                  double *fs, double *fnew, double *rho_out, double *u_out) {
     const size_t cells = (size_t)nx * ny * nz;
     int opp[Q];
@@ -181,7 +188,13 @@ void orc_lb_step(int nx, int ny, int nz, int zbc, double tau, const double *f,
                 for (int q = 0; q < Q; ++q) {
                     int ks = k - CV[q][2];
                     if (zbc == 0 && (ks < 0 || ks >= nz)) {
-                        fnew[q * cells + x] = fs[opp[q] * cells + x];
+                        double v = fs[opp[q] * cells + x];
+                        if (uwall) {
+                            const double *uw = ks < 0 ? uwall : uwall + 2;
+                            const double cu = CV[q][0] * uw[0] + CV[q][1] * uw[1];
+                            v += 2.0 * WV[q] * rho_wall * cu * ICS2;
+                        }
+                        fnew[q * cells + x] = v;
                     } else {
                         size_t s = cidx(wrap1(i - CV[q][0], nx), wrap1(j - CV[q][1], ny),
                                         wrap1(ks, nz), nx, ny);
@@ -428,6 +441,39 @@ double orc_volume(int T, const int32_t *tri, const double *q) {
         v += (a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2]) / 6.0;
     }
     return v;
+}
+
+/*
+ * Moments of the volume a closed mesh encloses, about the point ref:
+ * out = {V, int x, int y, int z, int xx, int yy, int zz, int xy, int xz, int yz}.
+ * The solid is the signed sum of the tetrahedra (ref, a, b, c) of its
+ * triangles; over a tetrahedron with vertices p_0..p_3 (p_0 = ref = 0)
+ *   int dV = v,  int x_i dV = v/4 sum_k p_ki,
+ *   int x_i x_j dV = v/20 (sum_k p_ki p_kj + (sum_k p_ki)(sum_k p_kj)),
+ * v = a . (b x c) / 6.  Used for the deformation index of Sec. 4 (semi-axes
+ * of the ellipsoid with the same second moments).
+ */
+void orc_volume_moments(int T, const int32_t *tri, const double *q, const double *ref, double *out) {
+    for (int k = 0; k < 10; ++k) out[k] = 0.0;
+    static const int PI[6] = {0, 1, 2, 0, 0, 1}, PJ[6] = {0, 1, 2, 1, 2, 2};
+    for (int t = 0; t < T; ++t) {
+        double p[3][3];
+        for (int c = 0; c < 3; ++c)
+            for (int a = 0; a < 3; ++a) p[c][a] = q[3 * tri[3 * t + c] + a] - ref[a];
+        double bc[3];
+        cross(p[1], p[2], bc);
+        const double v = (p[0][0] * bc[0] + p[0][1] * bc[1] + p[0][2] * bc[2]) / 6.0;
+        double s[3];
+        for (int a = 0; a < 3; ++a) s[a] = p[0][a] + p[1][a] + p[2][a];
+        out[0] += v;
+        for (int a = 0; a < 3; ++a) out[1 + a] += v * s[a] / 4.0;
+        for (int m = 0; m < 6; ++m) {
+            const int i = PI[m], j = PJ[m];
+            double pp = 0.0;
+            for (int c = 0; c < 3; ++c) pp += p[c][i] * p[c][j];
+            out[4 + m] += v * (pp + s[i] * s[j]) / 20.0;
+        }
+    }
 }
 
 double orc_area(int T, const int32_t *tri, const double *q) {

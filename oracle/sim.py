@@ -6,7 +6,7 @@ One step t -> t+1, in the order the paper's coupling implies (Sec. 2):
   3. moments with the half-force correction, BGK collision with
      the Guo source (relaxation time tau_in inside the droplets,
      tau outside, when the box sets tau_in), streaming with
-     halfway bounce-back                                         (Eqs. 1-6)
+     halfway bounce-back on resting or moving walls              (Eqs. 1-6)
   4. interpolation of u^t (the velocity of step 3) at q^t      (Eq. 7)
   5. forward Euler advection q^{t+1} = q^t + U                 (Sec. 2)
 """
@@ -14,8 +14,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (inside, interp, lattice, lb_step, mass, max_u, mesh_observables, node_forces,
-               spread, volume, wetting_A)
+from . import (deformation, inside, interp, lattice, lb_step, mass, max_u, mesh_observables,
+               node_forces, spread, volume, wetting_A)
 
 
 class OracleSim:
@@ -76,9 +76,12 @@ class OracleSim:
                 tau_in = getattr(b, "tau_in", 0.0)
                 if tau_in > 0.0 and ds:
                     mask = self.inside_mask(bi)
+                uw = (tuple(getattr(b, "wall_lo", (0.0, 0.0))), tuple(getattr(b, "wall_hi", (0.0, 0.0))))
+                moving = any(v != 0.0 for w in uw for v in w)
                 fn, rho, u = lb_step(self.f[bi], b.tau, b.zbc, F, b.body_force,
                                      scratch=self._scratch[bi], out=self._spare[bi],
-                                     inside=mask, tau_in=tau_in)
+                                     inside=mask, tau_in=tau_in,
+                                     u_wall=uw if moving else None, rho_wall=b.rho0)
                 self._spare[bi] = self.f[bi]
                 for di in ds:
                     U = interp(u, b.zbc, self.q[di])
@@ -92,6 +95,8 @@ class OracleSim:
         per_drop = []
         for di, d in enumerate(self.drops):
             o = mesh_observables(d.tris, self.q[di], d.xi)
+            dfm = deformation(d.tris, self.q[di])
+            o["deformation"], o["inclination"] = dfm["D"], dfm["inclination"]
             o["step"] = self.step_count
             per_drop.append(o)
         per_box = [{"step": self.step_count, "mass": mass(f), "max_u": max_u(f)}
