@@ -192,6 +192,49 @@ def free_droplet(n: int = 32, r: float = 8.0, level: int = 3, tau: float = 1.0,
     return Workload(f"free-droplet-{n}", [box], [d], storage=F64)
 
 
+def paper_spreading(tau: float = 0.732, freq: int = 77, shape=(250, 250, 150), r0: float = 60.0,
+                    sigma: float = 0.001, storage: int = F32) -> Workload:
+    """The spreading runs of the paper's Sec. 3 at their own scale: a droplet
+    of volume 4/3 pi R0^3 (R0 = 60) standing as a 90 deg cap on the wall
+    spreads toward theta_eq = 60 deg; 250 x 250 x 150 lattice, a geodesic
+    mesh of 20 freq^2 triangles (freq = 77: 118,580, the paper's ~120,000),
+    xi = 0.05 R0, sigma = 0.001, lambda = 1 with tau in {0.56, 0.59, 0.732,
+    1.1}.  Time unit t_mu = mu R0 / sigma; the paper runs 50 t_mu and reports
+    h / R0 -> 0.96 in the Stokes limit.  The volume penalty follows the other
+    workloads (k_V = 2 sigma / R0)."""
+    nx, ny, nz = shape
+    xi = 0.05 * r0
+    v, t = _mesh.cap_geodesic(freq, r0, _deg(90.0), nx / 2.0, ny / 2.0, xi)
+    box = Box(nx, ny, nz, tau=tau)
+    d = Droplet(0, v, t, sigma=sigma, theta_eq=_deg(60.0), xi=xi, k_vol=2.0 * sigma / r0)
+    mu = (tau - 0.5) / 3.0
+    return Workload(f"paper-spreading-{nx}x{ny}x{nz}-tau{tau:g}", [box], [d], storage=storage,
+                    extra={"t_mu": mu * r0 / sigma, "r0": r0, "re": sigma * r0 / (mu * mu)})
+
+
+def shear_droplet(lam: float = 1.0, r: float = 12.0, ca: float = 0.05, re: float = 0.01,
+                  shape=(128, 96, 192), level: int = 5, tau_out: float = 1.0,
+                  storage: int = F32) -> Workload:
+    """Free droplet of radius r at the centre of a plane shear flow (paper
+    Sec. 4): walls at z = 0 and z = nz move with -/+ gamma nz / 2 along x;
+    viscosity ratio lam = (tau_in - 1/2) / (tau_out - 1/2); rho = 1.
+    Re = gamma r^2 / nu_out and Ca = mu_out gamma r / sigma fix the shear
+    rate gamma and sigma.  No wetting (theta = 180 deg) and no volume
+    penalty.  The paper's own run: r = 19, Re = 0.01, Ca = 0.05, tau = 1."""
+    nx, ny, nz = shape
+    nu = (tau_out - 0.5) / 3.0
+    gamma = re * nu / (r * r)
+    sigma = nu * gamma * r / ca
+    uw = gamma * nz / 2.0
+    box = Box(nx, ny, nz, tau=tau_out, tau_in=0.5 + lam * (tau_out - 0.5),
+              wall_lo=(-uw, 0.0), wall_hi=(uw, 0.0))
+    v, t = _mesh.sphere(level, r, (nx / 2.0, ny / 2.0, nz / 2.0))
+    d = Droplet(0, v, t, sigma=sigma, theta_eq=math.pi, xi=0.05 * r, k_vol=0.0)
+    return Workload(f"shear-droplet-lam{lam:g}-{nx}x{ny}x{nz}-r{r:g}", [box], [d], storage=storage,
+                    extra={"shear_rate": gamma, "ca": ca, "re": re, "lam": lam,
+                           "t_cap": ca / gamma})
+
+
 def perturbed_populations(box: Box, seed: int, amplitude: float = 1e-3) -> np.ndarray:
     """Random populations around the rest state, [19][nz][ny][nx] in the order
     of the velocity set passed later by the caller (weights w): returns a

@@ -88,6 +88,48 @@ def _icosphere_cached(level: int) -> tuple[np.ndarray, np.ndarray]:
     return np.array(v, dtype=np.float64), f.astype(np.int32)
 
 
+def geodesic(freq: int) -> tuple[np.ndarray, np.ndarray]:
+    """Unit geodesic sphere of frequency `freq`: every icosahedron face is cut
+    into freq^2 triangles on a regular barycentric grid and the grid points
+    are pushed onto the unit sphere.  N = 10 freq^2 + 2 nodes, T = 20 freq^2
+    triangles (freq = 2^L gives the level-L icosphere's counts; freq = 77
+    gives 118,580 triangles).  Points on shared edges and corners are merged
+    by their integer barycentric weights on the 12 icosahedron vertices."""
+    n = int(freq)
+    if n < 1:
+        raise ValueError("freq must be >= 1")
+    base = np.array([p / np.linalg.norm(p) for p in _ICO_V])
+    faces = _orient_outward(base, _ICO_F)
+    index: dict[tuple, int] = {}
+    pts: list[np.ndarray] = []
+
+    def node(a: int, b: int, c: int, i: int, j: int) -> int:
+        w = {}
+        for vid, wt in ((a, n - i - j), (b, i), (c, j)):
+            if wt:
+                w[vid] = w.get(vid, 0) + wt
+        key = tuple(sorted(w.items()))
+        k = index.get(key)
+        if k is None:
+            p = sum(base[vid] * wt for vid, wt in key) / n
+            pts.append(p / np.linalg.norm(p))
+            k = len(pts) - 1
+            index[key] = k
+        return k
+
+    tris = []
+    for a, b, c in faces:
+        g = {(i, j): node(a, b, c, i, j) for i in range(n + 1) for j in range(n + 1 - i)}
+        for i in range(n):
+            for j in range(n - i):
+                tris.append((g[(i, j)], g[(i + 1, j)], g[(i, j + 1)]))
+                if i + j + 2 <= n:
+                    tris.append((g[(i + 1, j)], g[(i + 1, j + 1)], g[(i, j + 1)]))
+    v = np.array(pts, dtype=np.float64)
+    f = _orient_outward(v, np.array(tris, dtype=np.int64))
+    return v, f.astype(np.int32)
+
+
 def sphere(level: int, radius: float, centre) -> tuple[np.ndarray, np.ndarray]:
     """Icosphere scaled to `radius` and moved to `centre`."""
     v, f = icosphere(level)
@@ -128,6 +170,39 @@ def cap_on_wall(level: int, radius: float, theta0: float, x: float, y: float,
     below = v[:, 2] < base
     v[below, 2] = base
     return v, f
+
+
+def cap_geodesic(freq: int, radius: float, theta0: float, x: float, y: float, base: float):
+    """Spherical cap of contact angle theta0 on the plane z = base, holding
+    the volume of a sphere of `radius`, meshed from the geodesic sphere of
+    frequency `freq` with node density about even over the cap and its base
+    disc.  A unit-sphere node at polar angle phi (from +z) and azimuth psi goes
+    onto the cap at polar angle theta0 * phi / phi_s when phi <= phi_s, else
+    onto the disc at radius a (pi - phi) / (pi - phi_s) (a = Rc sin theta0);
+    phi_s splits the sphere's area in the ratio of cap area to disc area."""
+    rc = cap_radius(radius, theta0)
+    v, f = geodesic(freq)
+    cap_area = 2.0 * np.pi * rc * rc * (1.0 - np.cos(theta0))
+    a = rc * np.sin(theta0)
+    disc_area = np.pi * a * a
+    # (1 - cos phi_s) / 2 = cap_area / (cap_area + disc_area)
+    phi_s = np.arccos(1.0 - 2.0 * cap_area / (cap_area + disc_area))
+    phi = np.arccos(np.clip(v[:, 2], -1.0, 1.0))
+    psi = np.arctan2(v[:, 1], v[:, 0])
+    out = np.empty_like(v)
+    on_cap = phi <= phi_s
+    al = theta0 * phi[on_cap] / phi_s
+    zc = base - rc * np.cos(theta0)       # centre of the cap's sphere
+    out[on_cap, 0] = rc * np.sin(al) * np.cos(psi[on_cap])
+    out[on_cap, 1] = rc * np.sin(al) * np.sin(psi[on_cap])
+    out[on_cap, 2] = zc + rc * np.cos(al)
+    rd = a * (np.pi - phi[~on_cap]) / (np.pi - phi_s)
+    out[~on_cap, 0] = rd * np.cos(psi[~on_cap])
+    out[~on_cap, 1] = rd * np.sin(psi[~on_cap])
+    out[~on_cap, 2] = base
+    out[:, 0] += x
+    out[:, 1] += y
+    return out, f
 
 
 def is_closed_oriented(tris: np.ndarray) -> bool:

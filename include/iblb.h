@@ -98,6 +98,13 @@ typedef struct {
                            surface resolved as if moved by (+e, +e^2) in x, y
                            and a crossing at the centre's height counting as
                            below it.  Droplets of one box must not overlap. */
+    double wall_lo[2];  /* (u_x, u_y) of the wall at z = 0 and of the wall   */
+    double wall_hi[2];  /* at z = nz (IBLB_Z_WALLS only; zeros: resting).  A
+                           moving wall adds 6 w_i rho0 (c_i . u_w) to each
+                           population it reflects (halfway bounce-back on a
+                           moving wall); two walls moving apart drive the
+                           shear flow of the free-droplet test of Sec. 4.
+                           Each component finite, |u| <= 0.1.             */
 } iblb_box;
 
 typedef struct {
@@ -132,6 +139,14 @@ typedef struct {
                               z = z_min + xi (0 if none)                        */
     double theta_app;      /* 2 atan(height / contact_radius)                  */
     double centroid[3];    /* area-weighted surface centroid                    */
+    double deformation;    /* D = (r1 - r3) / (r1 + r3) in the x-z (shear)
+                              plane (Sec. 4): r1 >= r3 the semi-axes of the
+                              ellipsoid with the same second moments of
+                              volume about the volume centroid (an
+                              ellipsoid of semi-axis r has int x^2 dV =
+                              V r^2 / 5 along it), from the x-z block      */
+    double inclination;    /* angle of the r1 axis from x toward z, in
+                              (-pi/2, pi/2]                                  */
     int32_t n_crossings;
     uint32_t status_bits;
 } iblb_obs;

@@ -31,7 +31,7 @@ EXPORTS = (
 class iblb_box(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("zbc", C.c_int32),
                 ("tau", C.c_double), ("rho0", C.c_double), ("body_force", C.c_double * 3),
-                ("tau_in", C.c_double)]
+                ("tau_in", C.c_double), ("wall_lo", C.c_double * 2), ("wall_hi", C.c_double * 2)]
 
 
 class iblb_droplet(C.Structure):
@@ -52,7 +52,8 @@ class iblb_obs(C.Structure):
     _fields_ = [("step", C.c_int64), ("volume", C.c_double), ("area", C.c_double),
                 ("z_min", C.c_double), ("z_max", C.c_double), ("height", C.c_double),
                 ("contact_radius", C.c_double), ("theta_app", C.c_double),
-                ("centroid", C.c_double * 3), ("n_crossings", C.c_int32),
+                ("centroid", C.c_double * 3), ("deformation", C.c_double),
+                ("inclination", C.c_double), ("n_crossings", C.c_int32),
                 ("status_bits", C.c_uint32)]
 
 
@@ -144,7 +145,9 @@ def make_config(workload, storage=None, flags=0, dev_scale=None):
     for k, b in enumerate(workload.boxes):
         boxes[k] = iblb_box(b.nx, b.ny, b.nz, b.zbc, b.tau, b.rho0,
                             (C.c_double * 3)(*[float(v) for v in b.body_force]),
-                            float(getattr(b, "tau_in", 0.0)))
+                            float(getattr(b, "tau_in", 0.0)),
+                            (C.c_double * 2)(*[float(v) for v in getattr(b, "wall_lo", (0.0, 0.0))]),
+                            (C.c_double * 2)(*[float(v) for v in getattr(b, "wall_hi", (0.0, 0.0))]))
     drops = (iblb_droplet * max(nd, 1))()
     keep = [boxes, drops]
     for k, d in enumerate(workload.droplets):
@@ -220,6 +223,7 @@ class Simulation:
                           "z_max": o.z_max, "height": o.height, "contact_radius": o.contact_radius,
                           "theta_app": o.theta_app, "cx": o.centroid[0], "cy": o.centroid[1],
                           "cz": o.centroid[2], "n_crossings": o.n_crossings,
+                          "deformation": o.deformation, "inclination": o.inclination,
                           "status_bits": o.status_bits})
         out_b = [{"step": b.step, "mass": b.mass, "max_u": b.max_u, "status_bits": b.status_bits}
                  for b in boxes]

@@ -174,6 +174,13 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
         if (!(B.tau > 0.5) || !finite(B.tau)) return fail(err, IBLB_E_INVAL, nm + ": tau must exceed 1/2");
         if (!(B.tau_in == 0.0 || (B.tau_in > 0.5 && finite(B.tau_in))))
             return fail(err, IBLB_E_INVAL, nm + ": tau_in must be 0 or exceed 1/2");
+        for (int a = 0; a < 2; ++a) {
+            const double lo = B.wall_lo[a], hi = B.wall_hi[a];
+            if (!(finite(lo) && finite(hi) && std::fabs(lo) <= 0.1 && std::fabs(hi) <= 0.1))
+                return fail(err, IBLB_E_INVAL, nm + ": wall velocities must be finite with |u| <= 0.1");
+            if (B.zbc != IBLB_Z_WALLS && (lo != 0.0 || hi != 0.0))
+                return fail(err, IBLB_E_INVAL, nm + ": moving walls need zbc = IBLB_Z_WALLS");
+        }
         if (!(B.rho0 > 0) || !finite(B.rho0)) return fail(err, IBLB_E_INVAL, nm + ": rho0 must be > 0");
         for (int a = 0; a < 3; ++a)
             if (!finite(B.body_force[a])) return fail(err, IBLB_E_INVAL, nm + ": body force not finite");
@@ -818,6 +825,12 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
         D.omega_in = D.contrast ? 1.0 / H.b.tau_in : D.omega;
         D.guo_in = D.contrast ? 1.0 - 1.0 / (2.0 * H.b.tau_in) : D.guo;
         for (int k = 0; k < 2; ++k) D.mask[k] = D.contrast ? (uint64_t *)at(H.off_mask[k]) : nullptr;
+        D.uw[0] = H.b.wall_lo[0];
+        D.uw[1] = H.b.wall_lo[1];
+        D.uw[2] = H.b.wall_hi[0];
+        D.uw[3] = H.b.wall_hi[1];
+        D.moving = (D.uw[0] != 0.0 || D.uw[1] != 0.0 || D.uw[2] != 0.0 || D.uw[3] != 0.0) ? 1 : 0;
+        if (D.moving) P.moving = 1;
         if (D.contrast) {
             P.contrast = 1;
             P.mask_words = std::max(P.mask_words, (int32_t)((int64_t)D.nzw * D.ny * D.nx));
@@ -1019,6 +1032,16 @@ iblb_status iblb_observables(iblb_ctx *c, iblb_obs *per_drop, int32_t n_drops, i
             r.n_crossings = (int32_t)o[8];
             r.contact_radius = o[8] > 0 ? o[7] / o[8] : 0.0;
             r.theta_app = r.contact_radius > 0 ? 2.0 * std::atan(r.height / r.contact_radius) : 0.0;
+            // second moments about the volume centroid, x-z block; its
+            // eigenvalues are r^2 / 5 of the equivalent ellipsoid's semi-axes
+            {
+                const double V = o[9], cx = o[10] / V, cz = o[12] / V;
+                const double sxx = o[13] / V - cx * cx, szz = o[15] / V - cz * cz, sxz = o[17] / V - cx * cz;
+                const double h = 0.5 * (sxx + szz), d = std::sqrt(0.25 * (sxx - szz) * (sxx - szz) + sxz * sxz);
+                const double r1 = std::sqrt(5.0 * (h + d)), r3 = std::sqrt(std::max(5.0 * (h - d), 0.0));
+                r.deformation = (r1 - r3) / (r1 + r3);
+                r.inclination = 0.5 * std::atan2(2.0 * sxz, sxx - szz);
+            }
             r.status_bits = bits;
         }
     if (per_box)
@@ -1036,6 +1059,13 @@ iblb_status iblb_observables(iblb_ctx *c, iblb_obs *per_drop, int32_t n_drops, i
                                                " (1 rho, 2 Mach, 4 wall, 8 jump)");
     }
     return IBLB_OK;
+}
+
+// Moving-wall term of population i reflected at the lower (z = 0) or upper
+// wall: 6 w_i rho0 (c_i . u_w).
+double wall_term(const iblb_box &b, int i, bool lower) {
+    const double *u = lower ? b.wall_lo : b.wall_hi;
+    return 6.0 * w_of(i) * b.rho0 * (cx_of(i) * u[0] + cy_of(i) * u[1]);
 }
 
 iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_out) {
@@ -1061,13 +1091,17 @@ iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_o
                     for (int i = 0; i < Q; ++i) {
                         const int zs = z - cz_of(i);
                         size_t src;
-                        if (!zper && (zs < 0 || zs >= nz))
+                        double wall = 0.0;
+                        if (!zper && (zs < 0 || zs >= nz)) {
                             src = (size_t)opp_of(i) * H.plane + ((size_t)z * ny + y) * H.sx + x;
-                        else
+                            wall = wall_term(H.b, i, zs < 0);
+                        } else {
                             src = (size_t)i * H.plane +
                                   ((size_t)wrap(zs, nz) * ny + wrap(y - cy_of(i), ny)) * H.sx +
                                   wrap(x - cx_of(i), nx);
-                        f_out[(size_t)i * cells + cell] = w_of(i) * H.b.rho0 + decode(c, raw.data(), src);
+                        }
+                        f_out[(size_t)i * cells + cell] =
+                            w_of(i) * H.b.rho0 + (decode(c, raw.data(), src) + wall);
                     }
                 }
     }
@@ -1130,7 +1164,8 @@ iblb_status iblb_write_state(iblb_ctx *c, int32_t box, const double *f_in) {
                     const int zt = z + cz_of(i);
                     double v;
                     if (!zper && (zt < 0 || zt >= nz))
-                        v = f_in[(size_t)opp_of(i) * cells + ((size_t)z * ny + y) * nx + x];
+                        v = f_in[(size_t)opp_of(i) * cells + ((size_t)z * ny + y) * nx + x] -
+                            wall_term(H.b, opp_of(i), zt < 0);
                     else
                         v = f_in[(size_t)i * cells +
                                  ((size_t)wrap(zt, nz) * ny + wrap(y + cy_of(i), ny)) * nx +

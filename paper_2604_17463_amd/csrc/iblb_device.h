@@ -176,6 +176,23 @@ __device__ __forceinline__ RowAddr row_addr(int y, int z, int ny, int nz, int sx
     return a;
 }
 
+// Halfway bounce-back on a moving wall: a population reflected at the wall
+// z = 0 (c_z = +1 in the first layer) or at z = nz (c_z = -1 in the last)
+// also carries the momentum the wall imparts, 2 w_i rho0 (c_i . u_w) / c_s^2.
+// k = 6 rho0 s (u_x, u_y) of the lower wall, then of the upper wall, with s
+// the storage scale (g is in stored units).
+template <typename R>
+__device__ __forceinline__ void wall_shift(R (&g)[Q], bool wlo, bool whi, const R (&k)[4]) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int cz = cz_of(i);
+        if (cz == 0) continue;
+        const R kx = cz == 1 ? k[0] : k[2], ky = cz == 1 ? k[1] : k[3];
+        const R d = (R)w_of(i) * ((R)cx_of(i) * kx + (R)cy_of(i) * ky);
+        if (cz == 1 ? wlo : whi) g[i] += d;
+    }
+}
+
 // Byte offsets of cell x and of its periodic x-neighbours x - 1, x + 1
 // within a row.
 struct XOff {

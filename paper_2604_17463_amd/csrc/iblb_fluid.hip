@@ -15,8 +15,8 @@ namespace iblb {
 // lives in scalar registers.  NT: the populations are written with
 // streaming stores (they are read again only in the next step; pays off
 // once the two population buffers exceed the last-level cache).  EXT: some
-// box has a viscosity contrast (the plain variant carries none of its
-// registers).  Cells next to a mesh are recomputed by the band kernel
+// box has a viscosity contrast or a moving wall (the plain variant carries
+// none of their registers).  Cells next to a mesh are recomputed by the band kernel
 // afterwards.
 template <int ST, bool UROW, bool NT, int CPT, bool EXT>
 __global__ void __launch_bounds__(K1_MAX_THREADS)
@@ -40,8 +40,11 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
         IBLB_GLOBAL char *__restrict__ dst = (IBLB_GLOBAL char *)B->f[parity ^ 1];
         const R omega = (R)B->omega, guo = (R)B->guo, rho0 = (R)B->rho0;
         const R omega_in = (R)B->omega_in, guo_in = (R)B->guo_in;
-        const bool contrast = B->contrast != 0;
+        const bool contrast = B->contrast != 0, moving = B->moving != 0;
         const IBLB_GLOBAL uint64_t *mprev = (const IBLB_GLOBAL uint64_t *)B->mask[parity ^ 1];
+        R kw[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) kw[a] = (R)(6.0 * B->rho0 * (double)scale * B->uw[a]);
         const R gx = (R)B->g[0], gy = (R)B->g[1], gz = (R)B->g[2];
         IBLB_GLOBAL R *__restrict__ uf = (IBLB_GLOBAL R *)B->ufull;
         const uint64_t plane = (uint64_t)B->plane;
@@ -86,6 +89,7 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                     R out[Q], u[3], rho;
                     const uint32_t own = ra[k].ro[1][1] + xo.c;
                     R om = omega, gu = guo;
+                    if (EXT && moving && (ra[k].wlo || ra[k].whi)) wall_shift<R>(g[k], ra[k].wlo, ra[k].whi, kw);
                     if (EXT && contrast) {
                         // inside bits of the previous step: a cell whose bit
                         // changes since then lies in the band, which the band
@@ -335,6 +339,12 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
         if (!inside) continue;
         R out[Q], u[3], rho;
         const uint32_t own = ra.ro[1][1] + xo.c;
+        if (B->moving && (ra.wlo || ra.whi)) {
+            R kw[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) kw[a] = (R)(6.0 * B->rho0 * (double)scale * B->uw[a]);
+            wall_shift<R>(g, ra.wlo, ra.whi, kw);
+        }
         R om = (R)B->omega, gu = (R)B->guo;
         if (B->contrast) {  // this step's inside bits
             const uint64_t w = ((const IBLB_GLOBAL uint64_t *)B->mask[parity])[((int64_t)(cz >> 6) * B->ny + cy) * B->nx + cx];
@@ -407,6 +417,12 @@ __global__ void __launch_bounds__(256) k_box_obs(DevPtrs P, int box, int parity,
         for (int x = threadIdx.x; x < B.nx; x += 256) {
             R g[Q];
             pull<ST>(src, pb, ra, x, B.nx, inv, g);
+            if (B.moving && (ra.wlo || ra.whi)) {  // g holds unscaled deviations
+                R kw[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) kw[a] = (R)(6.0 * B.rho0 * B.uw[a]);
+                wall_shift<R>(g, ra.wlo, ra.whi, kw);
+            }
             double dr = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
@@ -447,7 +463,7 @@ __global__ void __launch_bounds__(256) k_box_obs_final(DevPtrs P, int box, int g
 template <int ST, bool UROW, bool NT>
 static void launch_bulk_c(const DevPtrs &P, int parity, int full_u, float scale, float inv, const Launch &L,
                           dim3 grid, dim3 block, hipStream_t s) {
-    if (P.contrast) {
+    if (P.contrast || P.moving) {
         if (UROW && L.cpt == 2)
             hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
         else

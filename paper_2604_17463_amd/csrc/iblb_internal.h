@@ -95,6 +95,8 @@ struct BoxDev {
     double omega_in, guo_in;    // the same with tau_in (cells inside droplets)
     int32_t contrast, nzw;      // tau_in set; 64-bit words per column (ceil(nz/64))
     uint64_t *mask[2];          // [nzw][ny][nx] inside bits, one set per step parity
+    double uw[4];               // moving walls: u_x, u_y at z = 0, then at z = nz
+    int32_t moving, pad;        // some wall velocity is nonzero
 };
 
 struct DropDev {
@@ -147,6 +149,7 @@ struct DevPtrs {
     int32_t Ntot, nblk, Ttot, n_chunks;
     int32_t n_rowgroups, total_tiles, obs_groups, n_cus;  // n_cus: compute units of the device
     int32_t contrast;           // some box has tau_in set
+    int32_t moving;             // some box has a moving wall
     int32_t mask_words;         // largest nzw*ny*nx over those boxes
 };
 
@@ -176,7 +179,9 @@ hipError_t launch_box_obs(const DevPtrs &P, int storage, int parity, float inv_s
                           hipStream_t s);
 hipError_t launch_drop_obs(const DevPtrs &P, bool f64, hipStream_t s);
 
-constexpr int OBS_DROP = 12; // vol, area, zmin, zmax, cx, cy, cz, rsum, count, -, -, -
+// vol, area, zmin, zmax, cx, cy, cz, rsum, count, then the volume moments
+// about the node mean m: V, int (x-m), int (x-m)(x-m)^T (xx yy zz xy xz yz)
+constexpr int OBS_DROP = 20;
 constexpr int OBS_BOX = 2;   // mass, max_u
 constexpr int OBS_GROUPS = 512;
 

@@ -605,7 +605,11 @@ __device__ __forceinline__ double block_minmax256(double v, double *sh, bool mx)
 }
 
 // Per droplet (one workgroup): z range, FP64 area, volume and area-weighted
-// centroid, then the edge crossings of z = z_min + xi.
+// centroid, then the edge crossings of z = z_min + xi, and the moments of
+// the enclosed volume about the node mean m (for the deformation index):
+// over the tetrahedron (m, a, b, c) of each triangle, with p the corners
+// relative to m, s = p_a + p_b + p_c and v = p_a . (p_b x p_c) / 6,
+//   int dV = v,  int x dV = v s / 4,  int x x^T dV = v (sum p p^T + s s^T) / 20.
 template <typename R>
 __global__ void __launch_bounds__(256) k_drop_obs(DevPtrs P) {
     __shared__ double sh[256];
@@ -621,6 +625,13 @@ __global__ void __launch_bounds__(256) k_drop_obs(DevPtrs P) {
     }
     zmin = block_minmax256(zmin, sh, false);
     zmax = block_minmax256(zmax, sh, true);
+    double mean[3];
+    for (int a = 0; a < 3; ++a) {
+        double s = 0;
+        for (int k = threadIdx.x; k < D.n_nodes; k += 256) s += pos(D.node_off + k, a);
+        mean[a] = block_sum256(s, sh) / (double)max(D.n_nodes, 1);
+    }
+    double mom[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     double vol = 0, area = 0, c0 = 0, c1 = 0, c2 = 0;
     for (int t = D.tri_off + threadIdx.x; t < D.tri_off + D.n_tris; t += 256) {
         double p[3][3];
@@ -643,7 +654,23 @@ __global__ void __launch_bounds__(256) k_drop_obs(DevPtrs P) {
         c0 += At * (p[0][0] + p[1][0] + p[2][0]) / 3.0;
         c1 += At * (p[0][1] + p[1][1] + p[2][1]) / 3.0;
         c2 += At * (p[0][2] + p[1][2] + p[2][2]) / 3.0;
+        double r[3][3];
+        for (int c = 0; c < 3; ++c)
+            for (int a = 0; a < 3; ++a) r[c][a] = pos(P.tri[3 * t + c], a) - mean[a];
+        const double v = (r[0][0] * (r[1][1] * r[2][2] - r[1][2] * r[2][1]) +
+                          r[0][1] * (r[1][2] * r[2][0] - r[1][0] * r[2][2]) +
+                          r[0][2] * (r[1][0] * r[2][1] - r[1][1] * r[2][0])) / 6.0;
+        const double s[3] = {r[0][0] + r[1][0] + r[2][0], r[0][1] + r[1][1] + r[2][1],
+                             r[0][2] + r[1][2] + r[2][2]};
+        mom[0] += v;
+        for (int a = 0; a < 3; ++a) mom[1 + a] += v * s[a] / 4.0;
+        constexpr int I[6] = {0, 1, 2, 0, 0, 1}, J[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+            mom[4 + e] += v * (r[0][I[e]] * r[0][J[e]] + r[1][I[e]] * r[1][J[e]] + r[2][I[e]] * r[2][J[e]] +
+                               s[I[e]] * s[J[e]]) / 20.0;
     }
+    for (int e = 0; e < 10; ++e) mom[e] = block_sum256(mom[e], sh);
     vol = block_sum256(vol, sh);
     area = block_sum256(area, sh);
     c0 = block_sum256(c0, sh) / area + D.ref[0];
@@ -677,6 +704,7 @@ __global__ void __launch_bounds__(256) k_drop_obs(DevPtrs P) {
         o[6] = c2;
         o[7] = rs;
         o[8] = cnt;
+        for (int e = 0; e < 10; ++e) o[9 + e] = mom[e];
     }
 }
 

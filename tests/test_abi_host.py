@@ -78,6 +78,23 @@ def test_rejects_bad_box_parameters():
     assert _err(wl, storage=7) == B.IBLB_E_INVAL
 
 
+def test_rejects_bad_tau_in_and_wall_velocities():
+    wl = configs.plain_c1()
+    wl.boxes[0].tau_in = 0.4
+    assert _err(wl) == B.IBLB_E_INVAL
+    wl = configs.plain_c1()
+    wl.boxes[0].wall_hi = (0.2, 0.0)          # |u_w| above 0.1
+    assert _err(wl) == B.IBLB_E_INVAL
+    wl = configs.plain_c1()
+    wl.boxes[0].wall_lo = (0.0, float("inf"))
+    assert _err(wl) == B.IBLB_E_INVAL
+    wl = configs.free_droplet()              # z periodic: no walls to move
+    wl.boxes[0].wall_lo = (0.01, 0.0)
+    assert _err(wl) == B.IBLB_E_INVAL
+    for lam in (1.0, 3.0):
+        assert _size(configs.shear_droplet(lam=lam)) > 0
+
+
 def test_box_size_limit_of_the_stream_collide_addressing():
     # ten population planes are addressed with 32-bit offsets from one base
     from iblb_inputs.configs import Box, Workload
