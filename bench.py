@@ -15,13 +15,16 @@ besides the headline it carries:
     errors against the stored FP64 oracle trace and against the FP64 run;
   - the 512x512x256 box with 16 droplets in FP32 and FP16-deviation storage;
   - the 64-box batched workload in one context against 64 sequential runs;
-  - the FP64 oracle timed on the host cores (cpu_baseline).
+  - the FP64 oracle timed on the host cores (cpu_baseline);
+  - with --paper-spreading, the paper's own spreading runs at their scale
+    (h / R0 against t / t_mu for the given tau values).
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -246,6 +249,33 @@ def variants(args, f32_drop, total_steps):
     return out
 
 
+def paper_spreading(taus, n_tmu):
+    """The paper's own spreading runs (Sec. 3) at their scale: 250x250x150,
+    118,580-triangle mesh, R0 = 60, 90 -> 60 deg, for each tau over n_tmu
+    units t_mu = mu R0 / sigma; h / R0 every t_mu / 2."""
+    from iblb_inputs import configs
+    out = {}
+    for tau in taus:
+        wl = configs.paper_spreading(tau)
+        sim = make_sim(wl, "f32")
+        tmu, r0 = wl.extra["t_mu"], wl.extra["r0"]
+        every = max(1, int(round(tmu / 2)))
+        n = int(round(2 * n_tmu))
+        rows, dt = [], 0.0
+        for _ in range(n):
+            dt += timed_steps(sim, every)
+            d, _ = sim.observables()
+            rows.append([round(d[0]["step"] / tmu, 3), round(d[0]["height"] / r0, 5),
+                         round(math.degrees(d[0]["theta_app"]), 3)])
+        sim.close()
+        out[f"tau{tau:g}"] = {"workload": wl.name, "re": wl.extra["re"], "t_mu": tmu,
+                              "steps": every * n, "mlups": round(wl.cells * every * n / dt / 1e6, 1),
+                              "ib_nodes": wl.nodes, "t_over_tmu_h_over_r0_theta": rows}
+        print(f"paper spreading tau {tau}: h/R0 {rows[-1][1]:.4f} at t/t_mu {rows[-1][0]:.1f}",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +291,10 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--paper-spreading", default="",
+                    help="comma-separated tau values: also run the paper-scale spreading runs "
+                         "(250x250x150, 118,580 triangles; about 2,500 steps/s)")
+    ap.add_argument("--paper-tmu", type=float, default=50.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -315,6 +349,9 @@ def main():
     }
     if not args.no_variants:
         out["variants"] = variants(args, drop, args.warmup + args.steps)
+    if args.paper_spreading:
+        out["paper_spreading"] = paper_spreading(
+            [float(t) for t in args.paper_spreading.split(",")], args.paper_tmu)
     if not args.no_cpu_baseline:
         from iblb_inputs import configs
         out["cpu_baseline"] = cpu_baseline(configs.spreading_c2(), args.cpu_seconds)
