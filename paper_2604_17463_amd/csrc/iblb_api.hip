@@ -21,6 +21,7 @@ thread_local std::string g_last_error = "no error";
 
 constexpr size_t ALIGN = 256;
 constexpr size_t BIG_ALIGN = 2u << 20;
+constexpr int MULTI = 8;          // steps per multi-step graph
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -352,6 +353,10 @@ struct iblb_ctx {
     DevPtrs P{};
     Launch L{};
     hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][advect first]
+    // MULTI consecutive steps from a pending advection, by starting parity:
+    // one launch instead of MULTI (the host cost of a launch is close to a
+    // step's device time at the sizes of the spreading workload)
+    hipGraphExec_t multi[2] = {nullptr, nullptr};
     bool pending = false;  // advection of the last step not yet applied
     int parity = 0;
     int64_t step = 0;
@@ -451,6 +456,11 @@ iblb_status flush(iblb_ctx *c) {
 }
 
 void drop_graphs(iblb_ctx *c) {
+    for (auto &e : c->multi)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
     for (auto &row : c->exec)
         for (auto &e : row)
             if (e) {
@@ -480,6 +490,24 @@ iblb_status build_graphs(iblb_ctx *c) {
             if (e != hipSuccess)
                 return set_err(c, IBLB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         }
+    if (c->plan.nblk == 0) return IBLB_OK;  // no advection: single steps only
+    for (int p = 0; p < 2; ++p) {
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+        iblb_status st = IBLB_OK;
+        for (int k = 0; k < MULTI && st == IBLB_OK; ++k) st = enqueue_step(c, c->capture, p ^ (k & 1), true);
+        hipError_t e = hipStreamEndCapture(c->capture, &g);
+        if (st != IBLB_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess)
+            return set_err(c, IBLB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->multi[p], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return set_err(c, IBLB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
     return IBLB_OK;
 }
 
@@ -610,29 +638,34 @@ iblb_status autotune(iblb_ctx *c) {
     // 2. with meshes present and the step replayed as graphs, a cap on the
     //    bulk grid is judged by whole steps: the workgroups it does not take
     //    leave CU slots to the mesh kernels that run beside it, at some cost
-    //    in bulk bandwidth.  Each candidate starts from the initial state.
+    //    in bulk bandwidth.  Under a cap, two rows per thread keep more loads
+    //    in flight per wave, so both are tried.  Each candidate starts from
+    //    the initial state.
     if (c->plan.nblk > 0 && (c->plan.flags & IBLB_FLAG_GRAPH)) {
         const int cus = c->P.n_cus;
         const int wpg = best.bx * best.by / 64;  // waves per workgroup
         double sbest = 1e300;
         Launch chosen = best;
-        for (int waves_per_cu : {0, 16, 12, 8, 6}) {
-            Launch L = best;
-            L.maxg = waves_per_cu ? std::max(1, cus * waves_per_cu / wpg) : 0;
-            c->L = L;
-            iblb_status st = upload_rows(c);
-            if (st != IBLB_OK) return st;
-            if (L.maxg && c->L.grid >= c->P.n_rowgroups) continue;  // no cap at this size
-            double ms = 0;
-            st = reset_state(c);
-            if (st == IBLB_OK) st = build_graphs(c);
-            if (st == IBLB_OK) st = time_steps(c, &ms);
-            if (st != IBLB_OK) return st;
-            if (ms < sbest) {
-                sbest = ms;
-                chosen = L;
+        for (int waves_per_cu : {0, 16, 12, 8, 6})
+            for (int cpt : {1, 2}) {
+                Launch L = best;
+                L.cpt = cpt;
+                if (launch_problem(L)) continue;
+                L.maxg = waves_per_cu ? std::max(1, cus * waves_per_cu / wpg) : 0;
+                c->L = L;
+                iblb_status st = upload_rows(c);
+                if (st != IBLB_OK) return st;
+                if (L.maxg && c->L.grid >= c->P.n_rowgroups) continue;  // no cap at this size
+                double ms = 0;
+                st = reset_state(c);
+                if (st == IBLB_OK) st = build_graphs(c);
+                if (st == IBLB_OK) st = time_steps(c, &ms);
+                if (st != IBLB_OK) return st;
+                if (ms < sbest) {
+                    sbest = ms;
+                    chosen = L;
+                }
             }
-        }
         best = chosen;
         iblb_status st = reset_state(c);
         if (st != IBLB_OK) return st;
@@ -983,6 +1016,16 @@ iblb_status iblb_step(iblb_ctx *c, int64_t n) {
     if (c->unstable) return set_err(c, IBLB_E_STATE, "context is unstable; no further steps");
     for (int64_t k = 0; k < n; ++k) {
         const int a = c->pending ? 1 : 0;
+        if (a && n - k >= MULTI && c->multi[c->parity]) {
+            // MULTI steps, each starting with the previous step's advection
+            HIPCHK(c, hipGraphLaunch(c->multi[c->parity], c->stream));
+            c->parity ^= MULTI & 1;
+            c->step += MULTI;
+            c->epoch += MULTI;
+            c->last_step_epoch = c->epoch;
+            k += MULTI - 1;
+            continue;
+        }
         if (c->exec[c->parity][a]) {
             HIPCHK(c, hipGraphLaunch(c->exec[c->parity][a], c->stream));
         } else {
