@@ -290,40 +290,66 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
 // the spread force, then (COLLIDE) pull, collide with F = body force +
 // spread force, store the populations over the bulk result and write u to
 // the band; or (!COLLIDE, inspection) store F in the band.
-template <int ST, bool COLLIDE>
+// ONE_BOX: a single box, whose descriptor is read beside the list entry
+// rather than after it.
+template <int ST, bool COLLIDE, bool ONE_BOX>
 __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u, float scale, float inv) {
     using S = Stor<ST>;
     using R = typename S::R;
     constexpr uint32_t EB = sizeof(typename S::T);
     __shared__ int hits[4][64 * GATHER_GROUP];
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int nwaves = gridDim.x * 4;
-    // the epoch counter and both list lengths in one round trip
-    const int ctr = *P.ctr, n0 = P.tile_count[0], n1 = P.tile_count[1];
-    const int count = min((ctr & 1) ? n1 : n0, P.total_tiles);
     const IBLB_CONST int32_t *tl = (const IBLB_CONST int32_t *)P.tile_list;
+    // the epoch counter, both list lengths and the wave's first list entry
+    // in one round trip (the entry lies in the list whatever the count; the
+    // count decides whether it is used)
+    const int ctr = *P.ctr, n0 = P.tile_count[0], n1 = P.tile_count[1];
+    const int first = min(wave, P.total_tiles - 1);
+    const int first_gt = tl[2 * first], first_box = ONE_BOX ? 0 : tl[2 * first + 1];
+    // the descriptor fields the tile's addressing needs (box 0's when there
+    // is one box: then they load beside the entry)
+    struct Geo {
+        int tile_base, tnx, tny, nx, ny, nz, sx, zbc;
+        uint64_t plane;
+        const void *src;
+    };
+    auto geo = [&](const IBLB_CONST BoxDev *B) {
+        return Geo{B->tile_base, B->tnx, B->tny, B->nx, B->ny, B->nz, B->sx, B->zbc, (uint64_t)B->plane,
+                   B->f[parity]};
+    };
+    Geo g0{};
+    if constexpr (ONE_BOX) g0 = geo((const IBLB_CONST BoxDev *)P.boxes);
+    // keep these loads beside the counter's (not after the count test)
+    asm volatile("" ::"s"(ctr), "s"(n0), "s"(n1), "s"(first_gt), "s"(first_box), "s"(g0.tile_base),
+                 "s"(g0.tnx), "s"(g0.tny), "s"(g0.nx), "s"(g0.ny), "s"(g0.nz), "s"(g0.sx), "s"(g0.zbc),
+                 "s"(g0.plane), "s"(g0.src));
+    const int count = min((ctr & 1) ? n1 : n0, P.total_tiles);
     for (int i = wave; i < count; i += nwaves) {
-        const int gt = tl[2 * i], box = tl[2 * i + 1];  // global tile id and its box
+        // global tile id and its box
+        const int gt = i == wave ? first_gt : tl[2 * i];
+        const int box = ONE_BOX ? 0 : (i == wave ? first_box : tl[2 * i + 1]);
         const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + box;
-        const int lt = gt - B->tile_base;
-        const int tx = lt % B->tnx, ty = (lt / B->tnx) % B->tny, tz = lt / (B->tnx * B->tny);
+        const Geo G = ONE_BOX ? g0 : geo(B);
+        const int lt = gt - G.tile_base;
+        const int tx = lt % G.tnx, ty = (lt / G.tnx) % G.tny, tz = lt / (G.tnx * G.tny);
         const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
-        const int x1 = min(x0 + TX - 1, B->nx - 1), y1 = min(y0 + TY - 1, B->ny - 1),
-                  z1 = min(z0 + TZ - 1, B->nz - 1);
+        const int x1 = min(x0 + TX - 1, G.nx - 1), y1 = min(y0 + TY - 1, G.ny - 1),
+                  z1 = min(z0 + TZ - 1, G.nz - 1);
         const int cx = x0 + (lane & (TX - 1)), cy = y0 + ((lane >> TXS) & (TY - 1)),
                   cz = z0 + (lane >> (TXS + TYS));
-        const bool inside = cx < B->nx && cy < B->ny && cz < B->nz;
+        const bool inside = cx < G.nx && cy < G.ny && cz < G.nz;
         // the populations are pulled first so that their loads are in flight
         // during the force gather
-        const uint64_t pb = (uint64_t)B->plane * EB;
-        const PopRes rs = pop_res(B->f[parity], pb);
+        const uint64_t pb = G.plane * EB;
+        const PopRes rs = pop_res(G.src, pb);
         RowAddr ra{};
         XOff xo{};
         R g[Q];
         if (COLLIDE && inside) {
-            ra = row_addr(cy, cz, B->ny, B->nz, B->sx, B->zbc == 1, EB);
-            xo = x_off<EB>(cx, B->nx);
+            ra = row_addr(cy, cz, G.ny, G.nz, G.sx, G.zbc == 1, EB);
+            xo = x_off<EB>(cx, G.nx);
             pull_buf<ST, true>(rs, (uint32_t)pb, ra, xo, g);
         }
         R F0 = 0, F1 = 0, F2 = 0;
@@ -510,7 +536,12 @@ hipError_t launch_bulk(const DevPtrs &P, int storage, int parity, int full_u, fl
 template <int ST, bool C>
 static void launch_band_t(const DevPtrs &P, int parity, int full_u, float scale, hipStream_t s) {
     const int grid = min((P.total_tiles + 3) / 4, 2048);
-    hipLaunchKernelGGL((k_band<ST, C>), dim3(grid), dim3(256), 0, s, P, parity, full_u, scale, 1.0f / scale);
+    if (P.n_boxes == 1)
+        hipLaunchKernelGGL((k_band<ST, C, true>), dim3(grid), dim3(256), 0, s, P, parity, full_u, scale,
+                           1.0f / scale);
+    else
+        hipLaunchKernelGGL((k_band<ST, C, false>), dim3(grid), dim3(256), 0, s, P, parity, full_u, scale,
+                           1.0f / scale);
 }
 
 hipError_t launch_band(const DevPtrs &P, int storage, int parity, int full_u, float scale, bool collide,
