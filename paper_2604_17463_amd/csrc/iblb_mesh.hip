@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
 // list does not affect any result).  Also clears the other epoch's count.
 __global__ void __launch_bounds__(256) k_compact(DevPtrs P) {
     const int lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int ctr = *P.ctr;
     const int slot = ctr & 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -449,6 +449,18 @@ __global__ void __launch_bounds__(256) k_interp(DevPtrs P, int mode, double *Uou
     }
     const int ex = bx1 - bx0 + 1, ey = by1 - by0 + 1, ez = bz1 - bz0 + 1;
     const bool staged = ex > 0 && ey > 0 && ez > 0 && (int64_t)ex * ey * ez <= MAXR;
+    // the node's own data load before the staging, so that they arrive
+    // beside it (j < Ntot: nodes are padded to whole blocks)
+    const int j = blk * NB + lane;
+    const R *wg = (const R *)P.wgt;
+    const int bx = P.base[j], by = P.base[N + j], bz = P.base[2 * N + j];
+    const R wz = wg[(8 + wave) * N + j];
+    R wx[4], wy[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        wx[o] = wg[o * N + j];
+        wy[o] = wg[(4 + o) * N + j];
+    }
     auto gidx = [&](int x, int y, int z) -> int64_t {
         return band_tile(x, y, z, B.tnx, B.tny) * 3 * TILE_CELLS + band_loc(x, y, z);
     };
@@ -488,21 +500,11 @@ __global__ void __launch_bounds__(256) k_interp(DevPtrs P, int mode, double *Uou
         }
     }
     __syncthreads();
-    const int j = blk * NB + lane;
     const bool valid = j - D.node_off < D.n_nodes;
     R U0 = 0, U1 = 0, U2 = 0;
     if (valid) {
-        const R *wg = (const R *)P.wgt;
-        const int bx = P.base[j], by = P.base[N + j], bz = P.base[2 * N + j];
         const int z = bz - 1 + wave;
         if (zper || (z >= 0 && z < B.nz)) {
-            const R wz = wg[(8 + wave) * N + j];
-            R wx[4], wy[4];
-#pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                wx[o] = wg[o * N + j];
-                wy[o] = wg[(4 + o) * N + j];
-            }
             if (staged) {
 #pragma unroll
                 for (int oy = 0; oy < 4; ++oy) {
