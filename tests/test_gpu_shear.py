@@ -157,3 +157,17 @@ def test_free_droplet_in_shear_reaches_taylor_deformation(lam, perm):
     assert 35.0 < math.degrees(d[0]["inclination"]) < 45.0
     assert abs(d[0]["volume"] / d0["volume"] - 1.0) < 0.005
     assert abs(d[0]["cz"] - wl.boxes[0].nz / 2.0) < 1e-3        # stays on the centre plane
+
+
+def test_moving_walls_graph_replay_is_bitwise_equal_to_eager():
+    # 37 steps: one single-step graph, four eight-step graphs, four single steps
+    say("moving walls graph vs eager")
+    wl = configs.shear_droplet(lam=2.0, r=6.0, ca=0.2, re=0.5, shape=(32, 24, 32), level=3,
+                               storage=F32)
+    a = sim(wl, F32, flags=0)
+    b = sim(wl, F32, flags=GRAPH)
+    a.step(37)
+    b.step(37)
+    assert np.array_equal(a.read_state(0), b.read_state(0))
+    assert np.array_equal(a.read_nodes(0), b.read_nodes(0))
+    assert a.observables()[0][0]["deformation"] == b.observables()[0][0]["deformation"]
