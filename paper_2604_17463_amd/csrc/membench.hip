@@ -51,6 +51,24 @@ __global__ void copy_planes(const float *__restrict__ a, float *__restrict__ b, 
     }
 }
 
+// The same with 2-byte elements (the FP16/BF16 deviation storage): one cell
+// per lane (2 B per access) or two neighbouring cells per lane (4 B).
+template <typename T, bool NT>
+__global__ void copy_planes_t(const T *__restrict__ a, T *__restrict__ b, size_t plane, size_t n) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T v[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) v[q] = a[q * plane + i];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        if (NT)
+            __builtin_nontemporal_store(v[q], b + q * plane + i);
+        else
+            b[q * plane + i] = v[q];
+    }
+}
+
 int main(int argc, char **argv) {
     size_t nx = 256, ny = 256, nz = 128;
     if (argc == 4) {
@@ -97,6 +115,38 @@ int main(int argc, char **argv) {
     const unsigned g = (unsigned)((n + 255) / 256);
     run("19-plane read/write, plain", [&] { copy_planes<false><<<g, 256>>>(a, b, plane, n); });
     run("19-plane read/write, streaming", [&] { copy_planes<true><<<g, 256>>>(a, b, plane, n); });
+    // 2-byte planes over the same cells: half the bytes per pass
+    const double bytes2 = bytes / 2;
+    auto run2 = [&](const char *name, auto launch) {
+        for (int w = 0; w < 3; ++w) launch();
+        CK(hipGetLastError());
+        CK(hipDeviceSynchronize());
+        float best = 1e30f;
+        for (int r = 0; r < 5; ++r) {
+            CK(hipEventRecord(e0));
+            for (int k = 0; k < 20; ++k) launch();
+            CK(hipEventRecord(e1));
+            CK(hipEventSynchronize(e1));
+            float ms = 0;
+            CK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / 20 < best) best = ms / 20;
+        }
+        std::printf("%-34s %9.1f us %8.1f GB/s\n", name, best * 1e3, bytes2 / (best * 1e-3) / 1e9);
+        std::fflush(stdout);
+    };
+    const unsigned g2 = (unsigned)((n / 2 + 255) / 256);
+    run2("2-byte planes, 2 B per lane", [&] {
+        copy_planes_t<unsigned short, false><<<g, 256>>>((const unsigned short *)a, (unsigned short *)b, plane, n);
+    });
+    run2("2-byte planes, 2 B per lane, NT", [&] {
+        copy_planes_t<unsigned short, true><<<g, 256>>>((const unsigned short *)a, (unsigned short *)b, plane, n);
+    });
+    run2("2-byte planes, 4 B per lane", [&] {
+        copy_planes_t<unsigned, false><<<g2, 256>>>((const unsigned *)a, (unsigned *)b, plane / 2, n / 2);
+    });
+    run2("2-byte planes, 4 B per lane, NT", [&] {
+        copy_planes_t<unsigned, true><<<g2, 256>>>((const unsigned *)a, (unsigned *)b, plane / 2, n / 2);
+    });
     CK(hipFree(a));
     CK(hipFree(b));
     return 0;
