@@ -230,6 +230,21 @@ iblb_status iblb_read_csr(struct iblb_ctx *ctx, int32_t d, int32_t *offsets, int
  * Synchronising. */
 iblb_status iblb_read_inside(struct iblb_ctx *ctx, int32_t b, uint8_t *inside_out);
 
+/* Checkpoints.  iblb_save_state writes the whole state of the current time
+ * into `blob` (host memory of exactly iblb_state_size bytes): the stored
+ * populations of every box as they are held (no rounding), the node
+ * positions as held, each droplet's reference volume V0, the step count
+ * and the status word.  iblb_load_state puts such a blob into a context
+ * built from the same configuration (boxes, storage, droplet parameters,
+ * meshes and initial node order; IBLB_E_INVAL otherwise): stepping on
+ * from there gives bit for bit what the saving context gives.  The inside
+ * bits are recomputed; the velocity of the last step is not kept (read_state
+ * reports NaN for it until the next step).  Both synchronise; save applies
+ * a pending advection first. */
+iblb_status iblb_state_size(const struct iblb_ctx *ctx, size_t *bytes);
+iblb_status iblb_save_state(struct iblb_ctx *ctx, void *blob, size_t bytes);
+iblb_status iblb_load_state(struct iblb_ctx *ctx, const void *blob, size_t bytes);
+
 /* Launch configuration of the fused stream-collide kernel:
  *   threads_x         threads along x per row, a multiple of 32;
  *   rows_per_group    rows of a workgroup; threads_x * rows_per_group must be

@@ -23,7 +23,8 @@ EXPORTS = (
     "iblb_velocity_set", "iblb_workspace_size", "iblb_init", "iblb_step", "iblb_observables",
     "iblb_read_state", "iblb_write_state", "iblb_read_nodes", "iblb_write_nodes",
     "iblb_compute_forces", "iblb_compute_spread", "iblb_interpolate", "iblb_read_bins",
-    "iblb_read_csr", "iblb_read_inside", "iblb_set_launch", "iblb_get_launch", "iblb_band_tile", "iblb_time_stream_collide",
+    "iblb_read_csr", "iblb_read_inside", "iblb_state_size", "iblb_save_state", "iblb_load_state",
+    "iblb_set_launch", "iblb_get_launch", "iblb_band_tile", "iblb_time_stream_collide",
     "iblb_destroy", "iblb_last_error",
 )
 
@@ -94,6 +95,9 @@ def load():
     L.iblb_read_bins.argtypes = [vp, i32, ip]
     L.iblb_read_csr.argtypes = [vp, i32, ip, ip]
     L.iblb_read_inside.argtypes = [vp, i32, C.POINTER(C.c_uint8)]
+    L.iblb_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.iblb_save_state.argtypes = [vp, vp, C.c_size_t]
+    L.iblb_load_state.argtypes = [vp, vp, C.c_size_t]
     L.iblb_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
     L.iblb_get_launch.argtypes = [vp, ip, ip, ip, ip, ip]
     L.iblb_band_tile.argtypes = [ip]
@@ -284,6 +288,19 @@ class Simulation:
         ent = np.empty(3 * len(dr.tris), np.int32)
         self._chk(load().iblb_read_csr(self.ctx, d, _iptr(off), _iptr(ent)))
         return off, ent
+
+    def save_state(self):
+        """The whole state of the current time as bytes (iblb_save_state)."""
+        n = C.c_size_t()
+        self._chk(load().iblb_state_size(self.ctx, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        self._chk(load().iblb_save_state(self.ctx, buf, n.value))
+        return bytes(buf)
+
+    def load_state(self, blob):
+        """Restore a state saved from a context of the same configuration."""
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        self._chk(load().iblb_load_state(self.ctx, buf, len(blob)))
 
     def read_inside(self, b=0):
         """Inside bits of box b at the current node positions, uint8 [nz][ny][nx]."""

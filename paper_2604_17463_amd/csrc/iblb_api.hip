@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -360,6 +361,7 @@ struct iblb_ctx {
     bool pending = false;  // advection of the last step not yet applied
     int parity = 0;
     int64_t step = 0;
+    bool u_valid = false;    // the full u field holds the last step's velocity
     int32_t epoch = 0;       // host mirror of the device step epoch
     int32_t last_step_epoch = -1;
     bool unstable = false;
@@ -1021,6 +1023,7 @@ iblb_status iblb_step(iblb_ctx *c, int64_t n) {
             HIPCHK(c, hipGraphLaunch(c->multi[c->parity], c->stream));
             c->parity ^= MULTI & 1;
             c->step += MULTI;
+            c->u_valid = true;
             c->epoch += MULTI;
             c->last_step_epoch = c->epoch;
             k += MULTI - 1;
@@ -1034,6 +1037,7 @@ iblb_status iblb_step(iblb_ctx *c, int64_t n) {
         }
         c->parity ^= 1;
         ++c->step;
+        c->u_valid = true;
         if (c->plan.nblk > 0) {
             if (a) ++c->epoch;  // the advection at the head of the step
             c->last_step_epoch = c->epoch;
@@ -1158,7 +1162,7 @@ iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_o
                     for (int x = 0; x < nx; ++x) {
                         const size_t k = (size_t)a * H.plane + ((size_t)z * ny + y) * H.sx + x;
                         const double v = R == 8 ? ((double *)uf.data())[k] : ((float *)uf.data())[k];
-                        u_out[(size_t)a * cells + ((size_t)z * ny + y) * nx + x] = c->step > 0 ? v : NAN;
+                        u_out[(size_t)a * cells + ((size_t)z * ny + y) * nx + x] = c->u_valid ? v : NAN;
                     }
     } else if (u_out) {
         const int R = c->plan.real;
@@ -1437,6 +1441,171 @@ iblb_status iblb_read_inside(iblb_ctx *c, int32_t b, uint8_t *inside_out) {
             for (int x = 0; x < nx; ++x)
                 inside_out[((size_t)z * ny + y) * nx + x] =
                     (uint8_t)((m[((size_t)(z >> 6) * ny + y) * nx + x] >> (z & 63)) & 1u);
+    return IBLB_OK;
+}
+
+// ---------------------------------------------------------- checkpoints
+// Blob: header, then per box its dimensions and the stored populations of
+// the current time (raw storage bytes, padding included), the node
+// positions as stored (hi and lo arrays), and per droplet its counts and
+// reference volume V0.  A fingerprint of the configuration (box fields,
+// storage, droplet parameters, node order and triangles) ties a blob to
+// contexts built from the same configuration.
+namespace {
+struct StateHeader {
+    char magic[8];
+    uint64_t fingerprint;
+    int64_t step;
+    int32_t storage, n_boxes, n_drops, Ntot;
+    uint32_t status;
+    int32_t real;
+};
+constexpr char STATE_MAGIC[8] = {'I', 'B', 'L', 'B', 'S', 'T', '0', '1'};
+
+uint64_t fnv(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+uint64_t fingerprint(const iblb_ctx *c) {
+    const Plan &p = c->plan;
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &p.storage, sizeof p.storage);
+    h = fnv(h, &p.scale, sizeof p.scale);
+    for (const BoxHost &H : p.boxes) {
+        const iblb_box &b = H.b;
+        const int32_t dims[4] = {b.nx, b.ny, b.nz, b.zbc};
+        const double prm[10] = {b.tau,    b.rho0,       b.body_force[0], b.body_force[1], b.body_force[2],
+                                b.tau_in, b.wall_lo[0], b.wall_lo[1],    b.wall_hi[0],    b.wall_hi[1]};
+        h = fnv(h, dims, sizeof dims);
+        h = fnv(h, prm, sizeof prm);
+    }
+    for (const DropHost &D : p.drops) {
+        const int32_t cnt[5] = {D.d.box, D.d.n_nodes, D.d.n_tris, D.d.n_exp, D.d.m_exp};
+        const double prm[4] = {D.d.sigma, D.d.theta_eq, D.d.xi, D.d.k_vol};
+        h = fnv(h, cnt, sizeof cnt);
+        h = fnv(h, prm, sizeof prm);
+        h = fnv(h, D.perm.data(), D.perm.size() * 4);
+        h = fnv(h, D.tris.data(), D.tris.size() * 4);
+    }
+    return h;
+}
+
+size_t state_bytes(const iblb_ctx *c) {
+    const Plan &p = c->plan;
+    size_t n = sizeof(StateHeader);
+    for (const BoxHost &H : p.boxes) n += 16 + (size_t)Q * H.plane * elem_bytes(p.storage);
+    n += (size_t)2 * 3 * p.Ntot * p.real;
+    n += (size_t)p.drops.size() * 16;
+    return n;
+}
+}  // namespace
+
+iblb_status iblb_state_size(const iblb_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return set_err(nullptr, IBLB_E_INVAL, "ctx or bytes is NULL");
+    *bytes = state_bytes(c);
+    return IBLB_OK;
+}
+
+iblb_status iblb_save_state(iblb_ctx *c, void *blob, size_t n) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (!blob || n != state_bytes(c)) return set_err(c, IBLB_E_INVAL, "blob is NULL or not iblb_state_size bytes");
+    {
+        iblb_status st = flush(c);
+        if (st != IBLB_OK) return st;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Plan &p = c->plan;
+    char *o = (char *)blob;
+    StateHeader hd{};
+    std::memcpy(hd.magic, STATE_MAGIC, 8);
+    hd.fingerprint = fingerprint(c);
+    hd.step = c->step;
+    hd.storage = p.storage;
+    hd.n_boxes = (int32_t)p.boxes.size();
+    hd.n_drops = (int32_t)p.drops.size();
+    hd.Ntot = p.Ntot;
+    hd.real = p.real;
+    HIPCHK(c, hipMemcpy(&hd.status, c->P.status, 4, hipMemcpyDeviceToHost));
+    std::memcpy(o, &hd, sizeof hd);
+    o += sizeof hd;
+    for (const BoxHost &H : p.boxes) {
+        const int32_t dims[4] = {H.b.nx, H.b.ny, H.b.nz, H.b.zbc};
+        std::memcpy(o, dims, 16);
+        o += 16;
+        const size_t bytes = (size_t)Q * H.plane * elem_bytes(p.storage);
+        HIPCHK(c, hipMemcpy(o, c->ws + H.off_f[c->parity], bytes, hipMemcpyDeviceToHost));
+        o += bytes;
+    }
+    const size_t qb = (size_t)3 * p.Ntot * p.real;
+    HIPCHK(c, hipMemcpy(o, c->P.qh, qb, hipMemcpyDeviceToHost));
+    o += qb;
+    HIPCHK(c, hipMemcpy(o, c->P.ql, qb, hipMemcpyDeviceToHost));
+    o += qb;
+    std::vector<DropDev> dd(p.drops.size());
+    if (!dd.empty())
+        HIPCHK(c, hipMemcpy(dd.data(), c->P.drops, dd.size() * sizeof(DropDev), hipMemcpyDeviceToHost));
+    for (size_t d = 0; d < p.drops.size(); ++d) {
+        const int32_t cnt[2] = {p.drops[d].d.n_nodes, p.drops[d].d.n_tris};
+        std::memcpy(o, cnt, 8);
+        std::memcpy(o + 8, &dd[d].V0, 8);
+        o += 16;
+    }
+    return IBLB_OK;
+}
+
+iblb_status iblb_load_state(iblb_ctx *c, const void *blob, size_t n) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (!blob || n != state_bytes(c)) return set_err(c, IBLB_E_INVAL, "blob is NULL or not iblb_state_size bytes");
+    const Plan &p = c->plan;
+    const char *o = (const char *)blob;
+    StateHeader hd;
+    std::memcpy(&hd, o, sizeof hd);
+    o += sizeof hd;
+    if (std::memcmp(hd.magic, STATE_MAGIC, 8) != 0) return set_err(c, IBLB_E_INVAL, "not an iblb state blob");
+    if (hd.fingerprint != fingerprint(c) || hd.storage != p.storage || hd.n_boxes != (int32_t)p.boxes.size() ||
+        hd.n_drops != (int32_t)p.drops.size() || hd.Ntot != p.Ntot || hd.real != p.real || hd.step < 0)
+        return set_err(c, IBLB_E_INVAL, "the blob was saved from a different configuration");
+    {
+        iblb_status st = flush(c);  // no advection may be left pending
+        if (st != IBLB_OK) return st;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (const BoxHost &H : p.boxes) {
+        int32_t dims[4];
+        std::memcpy(dims, o, 16);
+        o += 16;
+        if (dims[0] != H.b.nx || dims[1] != H.b.ny || dims[2] != H.b.nz || dims[3] != H.b.zbc)
+            return set_err(c, IBLB_E_INVAL, "the blob was saved from a different configuration");
+        const size_t bytes = (size_t)Q * H.plane * elem_bytes(p.storage);
+        HIPCHK(c, hipMemcpy(c->ws + H.off_f[c->parity], o, bytes, hipMemcpyHostToDevice));
+        o += bytes;
+    }
+    const size_t qb = (size_t)3 * p.Ntot * p.real;
+    HIPCHK(c, hipMemcpy(c->P.qh, o, qb, hipMemcpyHostToDevice));
+    o += qb;
+    HIPCHK(c, hipMemcpy(c->P.ql, o, qb, hipMemcpyHostToDevice));
+    o += qb;
+    for (size_t d = 0; d < p.drops.size(); ++d) {
+        double V0;
+        std::memcpy(&V0, o + 8, 8);
+        o += 16;
+        HIPCHK(c, hipMemcpy((char *)c->P.drops + d * sizeof(DropDev) + offsetof(DropDev, V0), &V0, 8,
+                            hipMemcpyHostToDevice));
+    }
+    HIPCHK(c, hipMemcpy(c->P.status, &hd.status, 4, hipMemcpyHostToDevice));
+    // both sets of inside bits from the loaded positions
+    for (int k = 0; k < 2; ++k) {
+        const iblb_status st = compute_masks(c, k, c->stream);
+        if (st != IBLB_OK) return st;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->step = hd.step;
+    c->pending = false;
+    c->last_step_epoch = -1;
+    c->u_valid = false;
+    c->unstable = false;
     return IBLB_OK;
 }
 
