@@ -38,6 +38,7 @@ HBM_PEAK_GBS = 8000.0
 STORAGE = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
 ELEM = {"f64": 8, "f32": 4, "f16dev": 2, "bf16dev": 2}
 BYTES_PER_NODE = 150.0  # per IB node and step: q, phi, weights, CSR, triangle records
+BYTES_PER_BAND_CELL = 24.0  # per cell of a stamped tile: spread force read, velocity write
 TRACE = os.path.join(ROOT, "tests", "golden", "spreading_trace_oracle.json")
 PTRACE = os.path.join(ROOT, "tests", "golden", "precision_trace_oracle_tau{tau:g}.json")
 OBS = ("height", "contact_radius", "volume", "area")
@@ -116,21 +117,34 @@ def traffic_record():
 
 
 def cpu_baseline(wl, seconds: float):
+    """The oracle on the host cores (all the process may use, then one
+    thread), on the same workload from its initial state."""
     import oracle
-    sim = oracle.OracleSim(wl)
-    sim.step(1)  # first touch of the arrays outside the timing
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        sim.step(1)
-        n += 1
-        dt = time.perf_counter() - t0
-        if dt >= seconds or n >= 10000:
-            break
-    return {"value": round(wl.cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    cores = len(os.sched_getaffinity(0))
+    oracle.set_threads(cores)
+
+    def rate(limit):
+        sim = oracle.OracleSim(wl)
+        sim.step(1)  # first touch of the arrays outside the timing
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            sim.step(1)
+            n += 1
+            dt = time.perf_counter() - t0
+            if dt >= limit or n >= 10000:
+                return n, dt
+
+    n, dt = rate(seconds)
+    used = oracle.num_threads()
+    oracle.set_threads(1)
+    n1, dt1 = rate(seconds / 3)
+    oracle.set_threads(cores)
+    return {"value": round(wl.cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": used,
+            "kind": "oracle", "value_1_thread": round(wl.cells * n1 / dt1 / 1e6, 3),
             "sample": f"{n} steps of the {wl.name} workload after its first step "
-                      f"({dt:.1f} s, FP64, OpenMP over z-slabs)"}
+                      f"({dt:.1f} s, FP64, OpenMP over z-slabs on {used} threads); "
+                      f"one thread: {n1} steps in {dt1:.1f} s"}
 
 
 def run_spreading(storage, warmup, steps, autotune=True):
@@ -332,7 +346,8 @@ def main():
                    "storage": args.storage, "graph": True, "bulk_launch": list(launch)},
         "ib_nodes_per_s": nodes * args.steps / dt,
         "bytes_per_cell_update": cell_bytes(args.storage),
-        "step_roofline_frac": (bytes_k1 + nodes * BYTES_PER_NODE) * args.steps / dt
+        "step_roofline_frac": (bytes_k1 + band * BYTES_PER_BAND_CELL + nodes * BYTES_PER_NODE)
+        * args.steps / dt
         / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -51,6 +51,7 @@ _d = _C.c_double
 
 def _declare(L):
     L.orc_num_threads.restype = _i
+    L.orc_set_threads.argtypes = [_i]
     L.orc_lattice.argtypes = [_ip, _dp, _ip]
     L.orc_feq.argtypes = [_d, _dp, _dp]
     L.orc_guo.argtypes = [_d, _dp, _dp, _dp]
@@ -94,6 +95,11 @@ def _i32(a):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def lattice():

@@ -67,6 +67,15 @@ static int opposite_of(int i) {
 static const double ICS2 = 3.0;      /* 1/c_s^2 */
 static const double ICS4 = 9.0;      /* 1/c_s^4 */
 
+/* Threads of the OpenMP loops from now on (n >= 1). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();
