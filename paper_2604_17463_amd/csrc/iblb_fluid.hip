@@ -1,7 +1,7 @@
 // Fluid kernels of the IBLB wetting step (gfx950): the bulk fused
 // pull-stream / moments / BGK-Guo collision over every cell with the body
 // force only, the band kernel that gathers the spread interface force for
-// each stamped 4x4x4 tile and redoes the collision of its 64 cells with it,
+// each stamped band tile and redoes the collision of its 64 cells with it,
 // and the per-box observables.
 #include "iblb_device.h"
 

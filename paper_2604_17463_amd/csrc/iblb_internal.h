@@ -5,9 +5,12 @@
 //     (sx = x pitch rounded up to a 128-byte row), storing deviations
 //     f_i - w_i rho0 (scaled for FP16); a buffer holds the post-collision
 //     populations of the last step and the next step pulls from it;
-//   - 4x4x4 tiles (64 cells = one wavefront): an epoch stamp per tile and,
-//     in tile-major order [tile][3][64], the velocity u written by the band
-//     kernel in stamped tiles (and the spread force F for inspection).
+//   - band tiles of 16x4x1 cells (64 cells = one wavefront): an epoch
+//     stamp per tile and, in tile-major order [tile][3][64], the velocity u
+//     written by the band kernel in stamped tiles (and the spread force F
+//     for inspection);
+//   - with a viscosity contrast, two sets of inside bits [ceil(nz/64)][ny][nx]
+//     (one 64-bit word per 64 cells of a column), by step parity.
 // Per droplet, nodes are renumbered once (recursive coordinate bisection of
 // the initial positions) into compact blocks of 64 (one wavefront), padded
 // per droplet.  Node arrays are SoA over the padded global node index.

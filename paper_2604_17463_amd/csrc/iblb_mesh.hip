@@ -1,7 +1,8 @@
 // Mesh kernels of the IBLB wetting step (gfx950): per-triangle records,
 // the node pass (interface forces, Peskin weights, tile stamps and the
 // block-partial spread), the stamped-tile list, interpolation with forward
-// Euler advection, and the per-droplet observables.
+// Euler advection, the inside bits of the viscosity contrast, and the
+// per-droplet observables.
 #include "iblb_device.h"
 
 namespace iblb {
