@@ -324,6 +324,8 @@ def main():
     _, flags = sim.compute_spread(0)
     band = int(flags.sum()) * 64
     k1_ms = sim.time_stream_collide(reps=200)
+    # the mesh kernels alone (nodes/s over their time, without the fluid)
+    mesh_ms = sim.time_mesh_chain(reps=200)
     bytes_k1 = cells * cell_bytes(args.storage)
     achieved = bytes_k1 / (k1_ms * 1e-3) / 1e9
     launch = sim.get_launch()
@@ -345,6 +347,8 @@ def main():
         "config": {"workload": wl.name, "cells": cells, "ib_nodes": nodes,
                    "storage": args.storage, "graph": True, "bulk_launch": list(launch)},
         "ib_nodes_per_s": nodes * args.steps / dt,
+        "ib_nodes_per_s_mesh_kernels": nodes / (mesh_ms * 1e-3),
+        "mesh_kernels_ms": mesh_ms,
         "bytes_per_cell_update": cell_bytes(args.storage),
         "step_roofline_frac": (bytes_k1 + band * BYTES_PER_BAND_CELL + nodes * BYTES_PER_NODE)
         * args.steps / dt

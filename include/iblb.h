@@ -277,6 +277,15 @@ iblb_status iblb_band_tile(int32_t *shape);
  * advanced; the mesh is not).  Synchronising. */
 iblb_status iblb_time_stream_collide(struct iblb_ctx *ctx, int32_t reps, double *ms_out);
 
+/* Average device time (ms) of the mesh kernels of one step (triangle
+ * records, node pass with stamps and partial spread, stamped-tile list,
+ * interpolation; with tau_in the inside bits), over `reps` eager
+ * repetitions on the context's stream, each in a fresh tile epoch.  The
+ * nodes do not move and the fluid is not touched; the last step's band
+ * velocities are dropped (read_state reports NaN for them until the next
+ * step).  0 when there are no droplets.  Synchronising. */
+iblb_status iblb_time_mesh_chain(struct iblb_ctx *ctx, int32_t reps, double *ms_out);
+
 /* Free host-side state and graphs (not the caller's workspace). */
 iblb_status iblb_destroy(struct iblb_ctx *ctx);
 

@@ -24,7 +24,7 @@ EXPORTS = (
     "iblb_read_state", "iblb_write_state", "iblb_read_nodes", "iblb_write_nodes",
     "iblb_compute_forces", "iblb_compute_spread", "iblb_interpolate", "iblb_read_bins",
     "iblb_read_csr", "iblb_read_inside", "iblb_state_size", "iblb_save_state", "iblb_load_state",
-    "iblb_set_launch", "iblb_get_launch", "iblb_band_tile", "iblb_time_stream_collide",
+    "iblb_set_launch", "iblb_time_mesh_chain", "iblb_get_launch", "iblb_band_tile", "iblb_time_stream_collide",
     "iblb_destroy", "iblb_last_error",
 )
 
@@ -96,6 +96,7 @@ def load():
     L.iblb_read_csr.argtypes = [vp, i32, ip, ip]
     L.iblb_read_inside.argtypes = [vp, i32, C.POINTER(C.c_uint8)]
     L.iblb_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.iblb_time_mesh_chain.argtypes = [vp, i32, C.POINTER(C.c_double)]
     L.iblb_save_state.argtypes = [vp, vp, C.c_size_t]
     L.iblb_load_state.argtypes = [vp, vp, C.c_size_t]
     L.iblb_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
@@ -323,4 +324,9 @@ class Simulation:
     def time_stream_collide(self, reps=10):
         ms = C.c_double()
         self._chk(load().iblb_time_stream_collide(self.ctx, int(reps), C.byref(ms)))
+        return ms.value
+
+    def time_mesh_chain(self, reps=10):
+        ms = C.c_double()
+        self._chk(load().iblb_time_mesh_chain(self.ctx, int(reps), C.byref(ms)))
         return ms.value

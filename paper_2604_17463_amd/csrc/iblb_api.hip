@@ -1666,6 +1666,44 @@ iblb_status iblb_time_stream_collide(iblb_ctx *c, int32_t reps, double *ms) {
     return time_k1(c, reps, ms);
 }
 
+iblb_status iblb_time_mesh_chain(iblb_ctx *c, int32_t reps, double *ms) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (reps < 1 || !ms) return set_err(c, IBLB_E_INVAL, "reps >= 1 and an output are required");
+    *ms = 0.0;
+    if (c->plan.nblk == 0) return IBLB_OK;
+    {
+        iblb_status st = flush(c);
+        if (st != IBLB_OK) return st;
+    }
+    const bool f64 = is_f64(c);
+    double *Udev = (double *)(c->ws + c->plan.off_uout);
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    HIPCHK(c, hipEventRecord(a, c->stream));
+    for (int r = 0; r < reps; ++r) {
+        // a fresh epoch each time, as the advection at the head of a step
+        // starts one; the nodes do not move (interpolation into a scratch U)
+        HIPCHK(c, launch_epoch(c->P, c->stream));
+        iblb_status st = compute_masks(c, c->parity, c->stream);
+        if (st != IBLB_OK) return st;
+        HIPCHK(c, launch_tri(c->P, f64, c->stream));
+        HIPCHK(c, launch_node(c->P, f64, 0, c->stream));
+        HIPCHK(c, launch_mask_check(c->P, c->parity, c->stream));
+        HIPCHK(c, launch_interp(c->P, f64, 1, Udev, c->stream));
+    }
+    HIPCHK(c, hipEventRecord(b, c->stream));
+    HIPCHK(c, hipEventSynchronize(b));
+    float t = 0;
+    HIPCHK(c, hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    c->epoch += reps;
+    c->last_step_epoch = -1;  // the band velocities no longer match the stamps
+    *ms = (double)t / reps;
+    return IBLB_OK;
+}
+
 iblb_status iblb_destroy(iblb_ctx *c) {
     if (!c) return IBLB_OK;
     drop_graphs(c);

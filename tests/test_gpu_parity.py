@@ -400,3 +400,18 @@ def test_spreading_step_matches_oracle_from_gpu_state(perm):
     drops, boxes = s.observables()
     assert boxes[0]["status_bits"] == 0
     assert abs(boxes[0]["mass"] - oracle.mass(ref.f[0])) < 1e-9 * oracle.mass(ref.f[0])
+
+
+@pytest.mark.parametrize("tau_in", [0.0, 1.4])
+def test_timing_the_mesh_chain_leaves_the_run_unchanged(tau_in):
+    say("mesh chain timing", tau_in)
+    wl = configs.plain_c1()
+    wl.boxes[0].tau_in = tau_in
+    a = sim(wl, F32, flags=GRAPH)
+    b = sim(wl, F32, flags=GRAPH)
+    a.step(30)
+    assert a.time_mesh_chain(reps=5) > 0.0
+    a.step(30)
+    b.step(60)
+    assert np.array_equal(a.read_state(0), b.read_state(0))
+    assert np.array_equal(a.read_nodes(0), b.read_nodes(0))
