@@ -415,3 +415,27 @@ def test_timing_the_mesh_chain_leaves_the_run_unchanged(tau_in):
     b.step(60)
     assert np.array_equal(a.read_state(0), b.read_state(0))
     assert np.array_equal(a.read_nodes(0), b.read_nodes(0))
+
+
+@pytest.mark.parametrize("storage", [F32, F16])
+def test_batch_with_boxes_without_droplets_equals_separate_runs(storage):
+    # boxes 0 and 2 hold no droplet (body-force channels, one z-periodic);
+    # box 1 the C1 droplet: each equals its own run bit for bit
+    say("batch with empty boxes", storage)
+    c1 = configs.plain_c1()
+    e0 = Box(20, 12, 16, tau=0.7, body_force=(2e-5, 0.0, 0.0))
+    e2 = Box(36, 8, 10, tau=1.2, zbc=1, body_force=(0.0, 1e-5, -1e-5))
+    d = c1.droplets[0]
+    d.box = 1
+    wl = Workload("mixed", [e0, c1.boxes[0], e2], [d], storage=storage)
+    s = sim(wl, storage, flags=GRAPH)
+    s.step(30)
+    singles = [Workload("e0", [e0], [], storage=storage), configs.plain_c1(),
+               Workload("e2", [e2], [], storage=storage)]
+    for k, one in enumerate(singles):
+        t = sim(one, storage, flags=GRAPH)
+        t.step(30)
+        assert np.array_equal(s.read_state(k), t.read_state(0)), k
+    t = sim(singles[1], storage, flags=GRAPH)
+    t.step(30)
+    assert np.array_equal(s.read_nodes(0), t.read_nodes(0))
