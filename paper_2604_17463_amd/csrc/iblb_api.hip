@@ -744,40 +744,12 @@ iblb_status iblb_workspace_size(const iblb_config *cfg, size_t *bytes) {
     return IBLB_OK;
 }
 
-iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
-                      iblb_ctx **out) {
-    if (!out) return set_err(nullptr, IBLB_E_INVAL, "out is NULL");
-    *out = nullptr;
-    iblb_ctx *c = new iblb_ctx();
-    std::string err;
-    iblb_status st = build_plan(cfg, c->plan, &err);
-    if (st != IBLB_OK) {
-        delete c;
-        return set_err(nullptr, st, err);
-    }
+// Device-side set-up of a context whose plan, workspace, streams and events
+// are in place: tables, meshes, initial state, launch shape, graphs.  On
+// failure the caller destroys the context.
+static iblb_status init_device(iblb_ctx *c) {
     Plan &p = c->plan;
-    if (!dev_workspace || ((uintptr_t)dev_workspace % ALIGN) != 0 || bytes < p.total) {
-        delete c;
-        return set_err(nullptr, IBLB_E_WORKSPACE,
-                       "workspace must be 256-byte aligned device memory of at least " +
-                           std::to_string(p.total) + " bytes");
-    }
-    c->ws = (char *)dev_workspace;
-    c->stream = (hipStream_t)hip_stream;
-    {
-        hipError_t e = hipStreamCreateWithFlags(&c->ib, hipStreamNonBlocking);
-        const char *what = "hipStreamCreateWithFlags";
-        if (e == hipSuccess) {
-            e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-            what = "hipEventCreateWithFlags";
-        }
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            const std::string m = std::string(what) + ": " + hipGetErrorString(e);
-            iblb_destroy(c);
-            return set_err(nullptr, IBLB_E_DEVICE, m);
-        }
-    }
+    iblb_status st = IBLB_OK;
     auto at = [&](size_t off) { return (void *)(c->ws + off); };
     DevPtrs &P = c->P;
     P.boxes = (BoxDev *)at(p.off_boxes);
@@ -972,11 +944,7 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
     HIPCHK(c, launch_set_v0(P, is_f64(c), c->stream));
     // inside bits of the initial positions in both sets
     for (int k = 0; k < 2 && st == IBLB_OK; ++k) st = compute_masks(c, k, c->stream);
-    if (st != IBLB_OK) {
-        g_last_error = c->err;
-        iblb_destroy(c);
-        return st;
-    }
+    if (st != IBLB_OK) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
 
     // default launch shape of the stream-collide kernel
@@ -1003,6 +971,44 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
             hipHostMalloc((void **)&c->host_status, 64, hipHostMallocDefault) != hipSuccess)
             st = set_err(c, IBLB_E_DEVICE, "pinned host buffer allocation failed");
     }
+    return st;
+}
+
+iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
+                      iblb_ctx **out) {
+    if (!out) return set_err(nullptr, IBLB_E_INVAL, "out is NULL");
+    *out = nullptr;
+    iblb_ctx *c = new iblb_ctx();
+    std::string err;
+    iblb_status st = build_plan(cfg, c->plan, &err);
+    if (st != IBLB_OK) {
+        delete c;
+        return set_err(nullptr, st, err);
+    }
+    Plan &p = c->plan;
+    if (!dev_workspace || ((uintptr_t)dev_workspace % ALIGN) != 0 || bytes < p.total) {
+        delete c;
+        return set_err(nullptr, IBLB_E_WORKSPACE,
+                       "workspace must be 256-byte aligned device memory of at least " +
+                           std::to_string(p.total) + " bytes");
+    }
+    c->ws = (char *)dev_workspace;
+    c->stream = (hipStream_t)hip_stream;
+    {
+        hipError_t e = hipStreamCreateWithFlags(&c->ib, hipStreamNonBlocking);
+        const char *what = "hipStreamCreateWithFlags";
+        if (e == hipSuccess) {
+            e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+            what = "hipEventCreateWithFlags";
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            const std::string m = std::string(what) + ": " + hipGetErrorString(e);
+            iblb_destroy(c);
+            return set_err(nullptr, IBLB_E_DEVICE, m);
+        }
+    }
+    st = init_device(c);
     if (st != IBLB_OK) {
         g_last_error = c->err;
         iblb_destroy(c);
