@@ -146,11 +146,19 @@ def test_bins_and_csr_are_bit_exact(storage):
 
 
 @pytest.mark.parametrize("storage", [F64, F32])
-@pytest.mark.parametrize("which", ["c1", "cap"])
+@pytest.mark.parametrize("which", ["c1", "cap", "wrap"])
 def test_spread_matches_oracle(storage, which):
     say("spread", storage, which)
     if which == "c1":
         wl = _c1_jittered()
+    elif which == "wrap":
+        # a droplet across every periodic side of a box whose x and y sizes
+        # are not multiples of the band tile (partial last tiles; stencils
+        # that wrap touch three tiles along an axis)
+        v, t = mesh.sphere(3, 4.0, (36.2, 22.6, 19.1))
+        v = configs.jitter_nodes(v, 11, 0.2)
+        wl = Workload("wrap", [Box(37, 23, 20, tau=0.9, zbc=1)],
+                      [Droplet(0, v, t, sigma=0.01, theta_eq=math.pi, xi=0.4)], storage=F64)
     else:
         v, t = mesh.cap_on_wall(3, 8.0, math.radians(150), 14.5, 17.25, 0.4)
         wl = Workload("cap", [Box(32, 28, 24, tau=0.9)],
