@@ -157,28 +157,37 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
             const Node3<R> qj = load_node(qh, ql, N, j);
             R st[3] = {0, 0, 0}, ns[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
             R chi = 0;
+            // batches of incident records: every load of a batch is issued
+            // (entries past the degree read triangle 0 and are not added)
+            // before the first is added, in ascending triangle order
+            constexpr int GB = sizeof(R) == 4 ? 8 : 4;
             const int e0 = P.csr_off[j], e1 = P.csr_off[j + 1];
-            for (int e = e0; e < e1; e += 8) {
-                int code[8];
+            for (int e = e0; e < e1; e += GB) {
+                int code[GB];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) code[k] = e + k < e1 ? P.csr_ent[e + k] : -1;
+                for (int k = 0; k < GB; ++k) code[k] = e + k < e1 ? P.csr_ent[e + k] : -1;
+                V4 r0[GB], r1[GB], rf[GB];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
+                for (int k = 0; k < GB; ++k) {
+                    const int cd = code[k] < 0 ? 0 : code[k];
+                    const int t = cd / 3, c = cd - 3 * t;
+                    r0[k] = tr[(int64_t)t * (TREC / 4)];
+                    r1[k] = tr[(int64_t)t * (TREC / 4) + 1];
+                    rf[k] = tr[(int64_t)t * (TREC / 4) + 2 + c];
+                }
+#pragma unroll
+                for (int k = 0; k < GB; ++k) {
                     if (code[k] < 0) continue;
-                    const int t = code[k] / 3, c = code[k] - 3 * t;
-                    const V4 r0 = tr[(int64_t)t * (TREC / 4)];
-                    const V4 r1 = tr[(int64_t)t * (TREC / 4) + 1];
-                    const V4 rf = tr[(int64_t)t * (TREC / 4) + 2 + c];
-                    chi += r0.x;
-                    ns[0] += r0.y;
-                    ns[1] += r0.z;
-                    ns[2] += r0.w;
-                    gv[0] += r1.x;
-                    gv[1] += r1.y;
-                    gv[2] += r1.z;
-                    st[0] += rf.x;
-                    st[1] += rf.y;
-                    st[2] += rf.z;
+                    chi += r0[k].x;
+                    ns[0] += r0[k].y;
+                    ns[1] += r0[k].z;
+                    ns[2] += r0[k].w;
+                    gv[0] += r1[k].x;
+                    gv[1] += r1[k].y;
+                    gv[2] += r1[k].z;
+                    st[0] += rf[k].x;
+                    st[1] += rf[k].y;
+                    st[2] += rf[k].z;
                 }
             }
             const R nl = R(1) / sqrt(ns[0] * ns[0] + ns[1] * ns[1] + ns[2] * ns[2]);
