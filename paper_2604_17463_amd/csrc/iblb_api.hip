@@ -525,22 +525,32 @@ const char *launch_problem(const Launch &L) {
 }
 static_assert(K1_MAX_THREADS == 256, "launch_problem() states the bound");
 
+// Two timing events, destroyed on every return path.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() = default;
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 iblb_status time_k1(iblb_ctx *c, int reps, double *ms) {
-    hipEvent_t a, b;
-    HIPCHK(c, hipEventCreate(&a));
-    HIPCHK(c, hipEventCreate(&b));
-    HIPCHK(c, hipEventRecord(a, c->stream));
+    EventPair ev;
+    HIPCHK(c, hipEventCreate(&ev.a));
+    HIPCHK(c, hipEventCreate(&ev.b));
+    HIPCHK(c, hipEventRecord(ev.a, c->stream));
     for (int r = 0; r < reps; ++r) {
         HIPCHK(c, launch_bulk(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, c->L,
                               c->stream));
         c->parity ^= 1;
     }
-    HIPCHK(c, hipEventRecord(b, c->stream));
-    HIPCHK(c, hipEventSynchronize(b));
+    HIPCHK(c, hipEventRecord(ev.b, c->stream));
+    HIPCHK(c, hipEventSynchronize(ev.b));
     float t = 0;
-    HIPCHK(c, hipEventElapsedTime(&t, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+    HIPCHK(c, hipEventElapsedTime(&t, ev.a, ev.b));
     *ms = (double)t / reps;
     return IBLB_OK;
 }
@@ -582,22 +592,20 @@ iblb_status reset_state(iblb_ctx *c) {
 
 // Mean device time (ms) of one graph-replayed step, best of three runs.
 iblb_status time_steps(iblb_ctx *c, double *ms) {
-    hipEvent_t a, b;
-    HIPCHK(c, hipEventCreate(&a));
-    HIPCHK(c, hipEventCreate(&b));
+    EventPair ev;
+    HIPCHK(c, hipEventCreate(&ev.a));
+    HIPCHK(c, hipEventCreate(&ev.b));
     iblb_status st = iblb_step(c, 20);
     *ms = 1e300;
     for (int rep = 0; rep < 3 && st == IBLB_OK; ++rep) {
-        HIPCHK(c, hipEventRecord(a, c->stream));
+        HIPCHK(c, hipEventRecord(ev.a, c->stream));
         st = iblb_step(c, 40);
-        HIPCHK(c, hipEventRecord(b, c->stream));
-        HIPCHK(c, hipEventSynchronize(b));
+        HIPCHK(c, hipEventRecord(ev.b, c->stream));
+        HIPCHK(c, hipEventSynchronize(ev.b));
         float t = 0;
-        HIPCHK(c, hipEventElapsedTime(&t, a, b));
+        HIPCHK(c, hipEventElapsedTime(&t, ev.a, ev.b));
         *ms = std::min(*ms, (double)t / 40);
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
     return st;
 }
 
@@ -1683,14 +1691,16 @@ iblb_status iblb_time_mesh_chain(iblb_ctx *c, int32_t reps, double *ms) {
     }
     const bool f64 = is_f64(c);
     double *Udev = (double *)(c->ws + c->plan.off_uout);
-    hipEvent_t a, b;
-    HIPCHK(c, hipEventCreate(&a));
-    HIPCHK(c, hipEventCreate(&b));
-    HIPCHK(c, hipEventRecord(a, c->stream));
+    EventPair ev;
+    HIPCHK(c, hipEventCreate(&ev.a));
+    HIPCHK(c, hipEventCreate(&ev.b));
+    c->last_step_epoch = -1;  // the band velocities no longer match the stamps
+    HIPCHK(c, hipEventRecord(ev.a, c->stream));
     for (int r = 0; r < reps; ++r) {
         // a fresh epoch each time, as the advection at the head of a step
         // starts one; the nodes do not move (interpolation into a scratch U)
         HIPCHK(c, launch_epoch(c->P, c->stream));
+        ++c->epoch;
         iblb_status st = compute_masks(c, c->parity, c->stream);
         if (st != IBLB_OK) return st;
         HIPCHK(c, launch_tri(c->P, f64, c->stream));
@@ -1698,14 +1708,10 @@ iblb_status iblb_time_mesh_chain(iblb_ctx *c, int32_t reps, double *ms) {
         HIPCHK(c, launch_mask_check(c->P, c->parity, c->stream));
         HIPCHK(c, launch_interp(c->P, f64, 1, Udev, c->stream));
     }
-    HIPCHK(c, hipEventRecord(b, c->stream));
-    HIPCHK(c, hipEventSynchronize(b));
+    HIPCHK(c, hipEventRecord(ev.b, c->stream));
+    HIPCHK(c, hipEventSynchronize(ev.b));
     float t = 0;
-    HIPCHK(c, hipEventElapsedTime(&t, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    c->epoch += reps;
-    c->last_step_epoch = -1;  // the band velocities no longer match the stamps
+    HIPCHK(c, hipEventElapsedTime(&t, ev.a, ev.b));
     *ms = (double)t / reps;
     return IBLB_OK;
 }
