@@ -12,14 +12,23 @@
  *   - Lattice units, dx = dt = 1, c_s^2 = 1/3.  Cell (i,j,k) of an
  *     nx x ny x nz box is centred at (i+1/2, j+1/2, k+1/2).  x and y are
  *     periodic.  In z the box is periodic (IBLB_Z_PERIODIC, test mode) or
- *     closed by resting no-slip walls on the planes z = 0 (the wetting
- *     surface) and z = nz (IBLB_Z_WALLS), realised as halfway bounce-back.
+ *     closed by no-slip walls on the planes z = 0 (the wetting surface) and
+ *     z = nz (IBLB_Z_WALLS), realised as halfway bounce-back; the walls
+ *     rest or move in their own plane (iblb_box.wall_lo / wall_hi).
  *   - Mesh node coordinates are unwrapped lattice coordinates; the height
  *     above the wall used by Pi is the node's z.
  *   - Every call returns an iblb_status (0 = success, < 0 = error) and
  *     never throws; iblb_last_error() gives the message of the last failure.
  *   - Device work is enqueued on the HIP stream given to iblb_init.
- *     Calls documented as "synchronising" wait for that stream.
+ *     Calls documented as "synchronising" wait for that stream.  A context
+ *     also owns a second non-blocking stream for the mesh kernels of a step
+ *     (and, with IBLB_FLAG_GRAPH, one for graph capture); each step forks
+ *     from and joins back into the caller's stream with events, so work the
+ *     caller enqueues on that stream afterwards sees the step's results.
+ *   - Calls on one context must not overlap (a context is not thread-safe);
+ *     separate contexts may be driven from separate threads.  Make every
+ *     call with the device current at iblb_init.  The message of a failure
+ *     without a context is kept per thread.
  *   - Host arrays passed in are read during the call and not retained.
  *   - The device workspace is owned by the caller, must stay allocated and
  *     untouched until iblb_destroy, and is never freed by the library.
