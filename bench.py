@@ -290,6 +290,67 @@ def paper_spreading(taus, n_tmu):
     return out
 
 
+def half_profile(q, tris, cx, cy, levels=12):
+    """Half-profile of a droplet mesh: at `levels` heights evenly spaced
+    between its lowest and highest node, the mean distance from the vertical
+    axis through (cx, cy) of the points where mesh edges cross that plane."""
+    import numpy as np
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]])
+    e = np.unique(np.sort(e, axis=1), axis=0)
+    a, b = q[e[:, 0]], q[e[:, 1]]
+    z0, z1 = q[:, 2].min(), q[:, 2].max()
+    out = []
+    for k in range(levels):
+        z = z0 + (k + 0.5) / levels * (z1 - z0)
+        m = (a[:, 2] - z) * (b[:, 2] - z) < 0
+        s = (z - a[m, 2]) / (b[m, 2] - a[m, 2])
+        p = a[m] + s[:, None] * (b[m] - a[m])
+        out.append((z, float(np.hypot(p[:, 0] - cx, p[:, 1] - cy).mean())))
+    return out
+
+
+def paper_sec4(n_cap, n_neck):
+    """The two wetting runs of the paper's Sec. 4 at their scale: the 90 deg
+    cap spreading to 45 deg (tau = 0.59, 250x250x150) over n_cap t_mu, and
+    the sphere released at xi above the wall (tau = 0.56, 300x300x250) over
+    n_neck t_mu; h / R0, r_c / R0 and the apparent angle every t_mu / 2, and
+    half-profiles (z / R0, r / R0) at the times the paper shows."""
+    from iblb_inputs import configs
+    out = {}
+    for key, wl, n_tmu, shown in (("cap45", configs.paper_cap45(), n_cap, (0, 4, 10, 70)),
+                                  ("neck", configs.paper_neck(), n_neck, (3, 18, 30, 48))):
+        sim = make_sim(wl, "f32")
+        tmu, r0 = wl.extra["t_mu"], wl.extra["r0"]
+        tris = wl.droplets[0].tris
+        every = max(1, int(round(tmu / 2)))
+        n = int(round(2 * n_tmu))
+        want = {int(round(2 * t)) for t in shown if t <= n_tmu}
+        rows, profiles, dt = [], {}, 0.0
+        d0 = sim.observables()[0][0]
+
+        def profile(d):
+            return [[round(z / r0, 4), round(r / r0, 4)]
+                    for z, r in half_profile(sim.read_nodes(0), tris, d["cx"], d["cy"])]
+        if 0 in want:
+            profiles["0"] = profile(d0)
+        for i in range(1, n + 1):
+            dt += timed_steps(sim, every)
+            d = sim.observables()[0][0]
+            rows.append([round(d["step"] / tmu, 3), round(d["height"] / r0, 5),
+                         round(d["contact_radius"] / r0, 5), round(math.degrees(d["theta_app"]), 3)])
+            if i in want:
+                profiles[f"{i / 2:g}"] = profile(d)
+            if i % 20 == 0:
+                print(f"paper sec4 {key}: t/t_mu {rows[-1][0]:.1f} h/R0 {rows[-1][1]:.4f}",
+                      file=sys.stderr, flush=True)
+        sim.close()
+        out[key] = {"workload": wl.name, "re": wl.extra["re"], "t_mu": tmu, "steps": every * n,
+                    "mlups": round(wl.cells * every * n / dt / 1e6, 1), "ib_nodes": wl.nodes,
+                    "volume_drift": d["volume"] / d0["volume"] - 1.0,
+                    "t_over_tmu_h_rc_over_r0_theta": rows, "half_profiles_z_r_over_r0": profiles}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +370,11 @@ def main():
                     help="comma-separated tau values: also run the paper-scale spreading runs "
                          "(250x250x150, 118,580 triangles; about 2,500 steps/s)")
     ap.add_argument("--paper-tmu", type=float, default=50.0)
+    ap.add_argument("--paper-sec4", action="store_true",
+                    help="also run the two wetting runs of Sec. 4 at their scale (45 deg cap, "
+                         "250x250x150; sphere released at the wall, 300x300x250)")
+    ap.add_argument("--paper-sec4-tmu", type=float, nargs=2, default=(70.0, 50.0),
+                    help="their lengths in t_mu")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -371,6 +437,8 @@ def main():
     if args.paper_spreading:
         out["paper_spreading"] = paper_spreading(
             [float(t) for t in args.paper_spreading.split(",")], args.paper_tmu)
+    if args.paper_sec4:
+        out["paper_sec4"] = paper_sec4(*args.paper_sec4_tmu)
     if not args.no_cpu_baseline:
         from iblb_inputs import configs
         out["cpu_baseline"] = cpu_baseline(configs.spreading_c2(), args.cpu_seconds)

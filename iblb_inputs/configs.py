@@ -193,7 +193,8 @@ def free_droplet(n: int = 32, r: float = 8.0, level: int = 3, tau: float = 1.0,
 
 
 def paper_spreading(tau: float = 0.732, freq: int = 77, shape=(250, 250, 150), r0: float = 60.0,
-                    sigma: float = 0.001, storage: int = F32) -> Workload:
+                    sigma: float = 0.001, theta_eq_deg: float = 60.0, start: str = "cap",
+                    storage: int = F32) -> Workload:
     """The spreading runs of the paper's Sec. 3 at their own scale: a droplet
     of volume 4/3 pi R0^3 (R0 = 60) standing as a 90 deg cap on the wall
     spreads toward theta_eq = 60 deg; 250 x 250 x 150 lattice, a geodesic
@@ -201,15 +202,42 @@ def paper_spreading(tau: float = 0.732, freq: int = 77, shape=(250, 250, 150), r
     xi = 0.05 R0, sigma = 0.001, lambda = 1 with tau in {0.56, 0.59, 0.732,
     1.1}.  Time unit t_mu = mu R0 / sigma; the paper runs 50 t_mu and reports
     h / R0 -> 0.96 in the Stokes limit.  The volume penalty follows the other
-    workloads (k_V = 2 sigma / R0)."""
+    workloads (k_V = 2 sigma / R0).  start = "sphere" places the sphere of
+    radius R0 with its lowest node at xi above the wall instead of the cap."""
     nx, ny, nz = shape
     xi = 0.05 * r0
-    v, t = _mesh.cap_geodesic(freq, r0, _deg(90.0), nx / 2.0, ny / 2.0, xi)
+    if start == "cap":
+        v, t = _mesh.cap_geodesic(freq, r0, _deg(90.0), nx / 2.0, ny / 2.0, xi)
+    elif start == "sphere":
+        v, t = _mesh.geodesic_above_wall(freq, r0, nx / 2.0, ny / 2.0, xi)
+    else:
+        raise ValueError("start must be 'cap' or 'sphere'")
     box = Box(nx, ny, nz, tau=tau)
-    d = Droplet(0, v, t, sigma=sigma, theta_eq=_deg(60.0), xi=xi, k_vol=2.0 * sigma / r0)
+    d = Droplet(0, v, t, sigma=sigma, theta_eq=_deg(theta_eq_deg), xi=xi, k_vol=2.0 * sigma / r0)
     mu = (tau - 0.5) / 3.0
-    return Workload(f"paper-spreading-{nx}x{ny}x{nz}-tau{tau:g}", [box], [d], storage=storage,
+    name = f"paper-{'spreading' if start == 'cap' else 'sphere'}-{nx}x{ny}x{nz}-tau{tau:g}"
+    if theta_eq_deg != 60.0:
+        name += f"-theta{theta_eq_deg:g}"
+    return Workload(name, [box], [d], storage=storage,
                     extra={"t_mu": mu * r0 / sigma, "r0": r0, "re": sigma * r0 / (mu * mu)})
+
+
+def paper_cap45(storage: int = F32) -> Workload:
+    """Sec. 4, first wetting case of the Basilisk comparison: the 90 deg cap of
+    the Sec. 3 runs spreads toward theta_eq = 45 deg at tau = 0.59 (mu = 0.03,
+    Re = 66.7) on the 250 x 250 x 150 lattice; the paper compares
+    half-profiles at t / t_mu = 0, 4, 10, 70."""
+    return paper_spreading(0.59, theta_eq_deg=45.0, storage=storage)
+
+
+def paper_neck(storage: int = F32) -> Workload:
+    """Sec. 4, inertial case: a sphere of radius R0 = 60 with its lowest node
+    at xi above the wall spreads toward theta_eq = 45 deg at tau = 0.56
+    (mu = 0.02, Re = 150) on a 300 x 300 x 250 lattice; a neck forms at the
+    contact line, the droplet flattens and bounces back toward a cap (the
+    paper shows profiles at t / t_mu = 3, 18, 30, 48)."""
+    return paper_spreading(0.56, shape=(300, 300, 250), theta_eq_deg=45.0, start="sphere",
+                           storage=storage)
 
 
 def shear_droplet(lam: float = 1.0, r: float = 12.0, ca: float = 0.05, re: float = 0.01,

@@ -136,14 +136,24 @@ def sphere(level: int, radius: float, centre) -> tuple[np.ndarray, np.ndarray]:
     return v * float(radius) + np.asarray(centre, dtype=np.float64), f
 
 
-def sphere_above_wall(level: int, radius: float, x: float, y: float, gap: float):
-    """Sphere whose lowest node sits at height `gap` above the wall z = 0."""
-    v, f = icosphere(level)
+def _place_above_wall(v, radius: float, x: float, y: float, gap: float):
     v = v * float(radius)
     v[:, 0] += x
     v[:, 1] += y
     v[:, 2] += gap - v[:, 2].min()
-    return v, f
+    return v
+
+
+def sphere_above_wall(level: int, radius: float, x: float, y: float, gap: float):
+    """Sphere whose lowest node sits at height `gap` above the wall z = 0."""
+    v, f = icosphere(level)
+    return _place_above_wall(v, radius, x, y, gap), f
+
+
+def geodesic_above_wall(freq: int, radius: float, x: float, y: float, gap: float):
+    """The same with the geodesic sphere of frequency `freq`."""
+    v, f = geodesic(freq)
+    return _place_above_wall(v, radius, x, y, gap), f
 
 
 def cap_radius(radius: float, theta0: float) -> float:

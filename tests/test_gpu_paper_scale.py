@@ -1,10 +1,15 @@
-"""The paper's own spreading run at its scale (Sec. 3, Fig. 2) on the GPU:
-250 x 250 x 150 lattice, a 118,580-triangle mesh, R0 = 60, 90 -> 60 deg.
-The boundary element data of the paper are not available, so this is the
-self-consistency check the paper allows: the Stokes-limit height h / R0
-of about 0.96 (tests/golden/paper_spreading_sec3.txt) and, at the highest
-Reynolds number of the paper (tau = 0.56, Re = 150), the drop below the
-final height followed by a recovery that the paper describes."""
+"""The paper's own spreading runs at their scale on the GPU.
+
+Sec. 3, Fig. 2: 250 x 250 x 150 lattice, a 118,580-triangle mesh, R0 = 60,
+90 -> 60 deg.  The boundary element data of the paper are not available,
+so this is the self-consistency check the paper allows: the Stokes-limit
+height h / R0 of about 0.96 (tests/golden/paper_spreading_sec3.txt) and, at
+the highest Reynolds number of the paper (tau = 0.56, Re = 150), the drop
+below the final height followed by a recovery that the paper describes.
+
+Sec. 4, inertial case (tests/golden/paper_spreading_sec4.txt): a sphere
+released next to the wall first touches it through a neck that widens while
+the droplet keeps its full height."""
 import math
 import os
 
@@ -17,11 +22,12 @@ from _helpers import say
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_spreading_sec3.txt")
+GOLDEN4 = os.path.join(os.path.dirname(__file__), "golden", "paper_spreading_sec4.txt")
 
 
-def _golden():
+def _golden(path=GOLDEN):
     out = {}
-    for line in open(GOLDEN):
+    for line in open(path):
         line = line.strip()
         if line and not line.startswith("#"):
             k, *v = line.split()
@@ -53,3 +59,41 @@ def test_paper_scale_spreading_at_re_150():
     assert min(h) < h[-1] - 0.01                       # undershoot, then recovery
     assert abs(math.degrees(d["theta_app"]) - g["THETA_EQ_DEG"][0]) < 3.0
     assert abs(d["volume"] / d0["volume"] - 1.0) < 1e-3
+
+
+def test_paper_scale_sphere_touches_the_wall_through_a_neck():
+    # measured over the first 6 t_mu: r_c / R0 0.381 -> 0.750 while h / R0
+    # stays at 2.000 -> 1.994; at 3 t_mu the cross-section 1/24 of the
+    # height above the lowest node has 0.58 of the widest radius.  (The
+    # whole run, bench.py --paper-sec4: the droplet flattens quickly after
+    # about 20 t_mu, falls to h / R0 = 0.684 at 35 t_mu and recovers to 0.716
+    # with an apparent angle of 44.7 deg at 50 t_mu.)
+    from bench import half_profile
+    g = _golden(GOLDEN4)
+    import paper_2604_17463_amd as P
+    say("paper-scale sphere at the wall, tau 0.56")
+    wl = configs.paper_neck()
+    b, d0 = wl.boxes[0], wl.droplets[0]
+    assert (b.nx, b.ny, b.nz) == tuple(int(v) for v in g["NECK_LATTICE"])
+    assert abs(b.tau - g["NECK_TAU"][0]) < 1e-12
+    assert abs(math.degrees(d0.theta_eq) - g["THETA_EQ_DEG"][0]) < 1e-9
+    assert abs(d0.xi / wl.extra["r0"] - g["XI_OVER_R0"][0]) < 1e-12
+    assert abs(d0.nodes[:, 2].min() - d0.xi) < 1e-9
+    s = P.Simulation(wl, storage=1, flags=1 | 2)
+    tmu, r0 = wl.extra["t_mu"], wl.extra["r0"]
+    v0 = s.observables()[0][0]["volume"]
+    rc, h = [], []
+    for k in range(6):
+        s.step(int(round(tmu)))
+        d = s.observables()[0][0]
+        rc.append(d["contact_radius"] / r0)
+        h.append(d["height"] / r0)
+        if k == 2:
+            prof = half_profile(s.read_nodes(0), d0.tris, d["cx"], d["cy"], levels=12)
+    assert all(r1 > r0_ for r0_, r1 in zip(rc, rc[1:]))      # the neck widens
+    assert 0.3 < rc[0] < 0.5 and rc[-1] > 0.65
+    assert min(h) > 1.98                                     # still at full height
+    radii = [r for _, r in prof]
+    assert radii[0] < 0.7 * max(radii)                       # a neck at the wall
+    assert abs(d["volume"] / v0 - 1.0) < 2e-3
+    s.close()

@@ -50,6 +50,35 @@ def test_sphere_volume_area_converge():
     assert abs(oracle.volume(t, v) - 4 * math.pi / 3) / (4 * math.pi / 3) < 1e-3
 
 
+def test_paper_sec4_workloads_follow_the_paper():
+    # the two wetting runs of Sec. 4 (tests/golden/paper_spreading_sec4.txt)
+    import os
+    from iblb_inputs import configs
+    g = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "paper_spreading_sec4.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            g[k] = [float(x) for x in v]
+    r0 = g["R0"][0]
+    wls = {"CAP": configs.paper_cap45(), "NECK": configs.paper_neck()}
+    for key, wl in wls.items():
+        b, d = wl.boxes[0], wl.droplets[0]
+        assert (b.nx, b.ny, b.nz) == tuple(int(x) for x in g[key + "_LATTICE"])
+        assert abs(b.tau - g[key + "_TAU"][0]) < 1e-12
+        assert abs(math.degrees(d.theta_eq) - g["THETA_EQ_DEG"][0]) < 1e-9
+        assert d.sigma == g["SIGMA"][0] and abs(d.xi - g["XI_OVER_R0"][0] * r0) < 1e-12
+        assert abs(len(d.tris) / g["TRIANGLES"][0] - 1.0) < 0.02
+        assert mesh.is_closed_oriented(d.tris)
+        # the volume of the sphere of radius R0 (mesh error of the 59,292 nodes)
+        assert abs(oracle.volume(d.tris, d.nodes) / (4 * math.pi * r0 ** 3 / 3) - 1.0) < 2e-3
+        assert abs(d.nodes[:, 2].min() - d.xi) < 1e-9
+    # the cap starts at 90 deg, the sphere as a sphere of radius R0
+    cap, neck = wls["CAP"].droplets[0].nodes, wls["NECK"].droplets[0].nodes
+    assert abs(cap[:, 2].max() - cap[:, 2].min() - mesh.cap_radius(r0, math.pi / 2)) < 0.05
+    c = neck.mean(axis=0)
+    assert np.abs(np.linalg.norm(neck - c, axis=1) / r0 - 1.0).max() < 1e-9
+
+
 def _jittered(level=1, r=2.0, amp=0.1, centre=(5.0, 6.0, 7.0)):
     v, t = mesh.sphere(level, r, centre)
     return v + RNG.uniform(-amp, amp, v.shape), t
