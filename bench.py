@@ -351,6 +351,44 @@ def paper_sec4(n_cap, n_neck):
     return out
 
 
+def paper_shear(n_cap):
+    """Sec. 4's free droplet in shear at the paper's own parameters: R0 = 19,
+    Re = 0.01, Ca = 0.05, tau_in = tau_out = 1 (lambda = 1), an ico5 mesh,
+    walls 8 R0 from the centre (204 x 152 x 304).  The fluid starts as the
+    Couette flow (its BGK equilibrium, built here from the library's velocity
+    set).  D / D_inf every capillary time mu R0 / sigma over n_cap of them;
+    the paper reports its IBLB run 2.7 % from D_inf."""
+    import numpy as np
+
+    import paper_2604_17463_amd as P
+    from iblb_inputs import configs
+    wl = configs.shear_droplet(lam=1.0, r=19.0, shape=(204, 152, 304), level=5)
+    box, gamma = wl.boxes[0], wl.extra["shear_rate"]
+    sim = make_sim(wl, "f32")
+    c, w = P.velocity_set()
+    u = gamma * (np.arange(box.nz) + 0.5 - box.nz / 2.0)
+    cu = c[:, 0][:, None] * u[None, :]
+    feq = w[:, None] * box.rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * u[None, :] ** 2)
+    sim.write_state(np.ascontiguousarray(
+        np.broadcast_to(feq[:, :, None, None], (19, box.nz, box.ny, box.nx))))
+    dinf = (19.0 + 16.0) / 32.0 * wl.extra["ca"]
+    tcap = wl.extra["t_cap"]
+    d0 = sim.observables()[0][0]
+    rows, dt = [], 0.0
+    for k in range(1, int(n_cap) + 1):
+        dt += timed_steps(sim, int(round(k * tcap)) - int(round((k - 1) * tcap)))
+        d = sim.observables()[0][0]
+        rows.append([k, round(d["deformation"] / dinf, 5), round(math.degrees(d["inclination"]), 3)])
+        print(f"paper shear: t/t_cap {k} D/D_inf {rows[-1][1]:.4f}", file=sys.stderr, flush=True)
+    sim.close()
+    return {"workload": wl.name, "cells": wl.cells, "ib_nodes": wl.nodes, "t_cap": tcap,
+            "steps": int(round(n_cap * tcap)), "mlups": round(wl.cells * n_cap * tcap / dt / 1e6, 1),
+            "d_inf": dinf, "final_rel_distance_from_d_inf": rows[-1][1] - 1.0,
+            "paper_rel_distance": {"iblb": 0.027, "vof": 0.013},
+            "volume_drift": d["volume"] / d0["volume"] - 1.0,
+            "t_over_tcap_d_over_dinf_inclination_deg": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,6 +413,9 @@ def main():
                          "250x250x150; sphere released at the wall, 300x300x250)")
     ap.add_argument("--paper-sec4-tmu", type=float, nargs=2, default=(70.0, 50.0),
                     help="their lengths in t_mu")
+    ap.add_argument("--paper-shear", type=float, default=0.0, metavar="N_CAP",
+                    help="also run the free droplet in shear at the paper's R0 = 19 for N_CAP "
+                         "capillary times (16 reach the plateau; about 10,800 steps each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -439,6 +480,8 @@ def main():
             [float(t) for t in args.paper_spreading.split(",")], args.paper_tmu)
     if args.paper_sec4:
         out["paper_sec4"] = paper_sec4(*args.paper_sec4_tmu)
+    if args.paper_shear > 0:
+        out["paper_shear"] = paper_shear(args.paper_shear)
     if not args.no_cpu_baseline:
         from iblb_inputs import configs
         out["cpu_baseline"] = cpu_baseline(configs.spreading_c2(), args.cpu_seconds)

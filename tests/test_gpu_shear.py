@@ -137,7 +137,7 @@ def test_free_droplet_in_shear_reaches_taylor_deformation(lam, perm):
     # Sec. 4: in the Stokes limit at small Ca the deformation index tends to
     # D_inf = (19 lam + 16) / (16 lam + 16) Ca (Eq. D_inf); the paper's own
     # run is 2.7 % off at lam = 1.  Here R = 12, Ca = 0.05, Re = 0.01 in a
-    # 128 x 96 x 192 channel (walls 8 R apart, which adds about 2 % of
+    # 128 x 96 x 192 channel (walls 8 R from the centre, which adds about 2 % of
     # confinement), 16 capillary times mu_out R / sigma from a Couette flow.
     # Measured: D / D_inf = 1.034 (lam = 1), 0.994 (lam = 3); 5 % allowed.
     say("taylor deformation", lam)
