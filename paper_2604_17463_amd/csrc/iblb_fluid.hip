@@ -535,7 +535,9 @@ hipError_t launch_bulk(const DevPtrs &P, int storage, int parity, int full_u, fl
 
 template <int ST, bool C>
 static void launch_band_t(const DevPtrs &P, int parity, int full_u, float scale, hipStream_t s) {
-    const int grid = min((P.total_tiles + 3) / 4, 2048);
+    // one wave per tile up to 32,768 waves (workgroups of four); large
+    // bands (many boxes or droplets) loop over the rest of the list
+    const int grid = min((P.total_tiles + 3) / 4, 8192);
     if (P.n_boxes == 1)
         hipLaunchKernelGGL((k_band<ST, C, true>), dim3(grid), dim3(256), 0, s, P, parity, full_u, scale,
                            1.0f / scale);
