@@ -425,6 +425,39 @@ def test_timing_the_mesh_chain_leaves_the_run_unchanged(tau_in):
     assert np.array_equal(a.read_nodes(0), b.read_nodes(0))
 
 
+def test_band_list_longer_than_the_band_grid_equals_separate_runs():
+    # nine boxes whose droplets stamp about 34,000 band tiles together, more
+    # than the band kernel's 32,768 waves, so that waves take a second tile
+    # from the list; alone, each box stamps about 3,800 (one tile per wave).
+    # Level-6 meshes (640 node blocks each) keep the node pass in its
+    # one-wave form both in the batch and alone (it spreads with four waves,
+    # in another summation order, when there are at most as many blocks as
+    # compute units).  The batch equals the separate runs bit for bit.
+    say("band list longer than the band grid")
+    rng = np.random.default_rng(11)
+    boxes, drops = [], []
+    for k in range(9):
+        r = 36.0
+        v, t = mesh.sphere_above_wall(6, r, 48.0 + rng.uniform(-2, 2), 48.0 + rng.uniform(-2, 2), 0.05 * r)
+        boxes.append(Box(96, 96, 96, tau=float(rng.uniform(0.7, 1.2))))
+        drops.append(Droplet(k, v, t, sigma=0.005, theta_eq=float(rng.uniform(0.8, 2.2)), xi=0.05 * r,
+                             k_vol=0.0))
+    wl = Workload("band-list", boxes, drops, storage=F32)
+    s = sim(wl, F32, flags=GRAPH)
+    stamped = sum(int(s.compute_spread(b)[1].sum()) for b in range(len(boxes)))
+    assert stamped > 32768, stamped
+    s.step(10)
+    for k in range(len(boxes)):
+        one = Workload("one", [boxes[k]], [Droplet(0, **{f: getattr(drops[k], f) for f in (
+            "nodes", "tris", "sigma", "theta_eq", "xi", "n_exp", "m_exp", "k_vol")})], storage=F32)
+        t = sim(one, F32, flags=GRAPH)
+        t.step(10)
+        assert np.array_equal(s.read_state(k), t.read_state(0)), k
+        assert np.array_equal(s.read_nodes(k), t.read_nodes(0)), k
+        t.close()
+    s.close()
+
+
 @pytest.mark.parametrize("storage", [F32, F16])
 def test_batch_with_boxes_without_droplets_equals_separate_runs(storage):
     # boxes 0 and 2 hold no droplet (body-force channels, one z-periodic);
