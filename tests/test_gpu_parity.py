@@ -388,6 +388,37 @@ def test_spreading_forces_match_oracle_at_full_size():
     assert np.abs(got - want).max() < 2e-5 * np.abs(want).max()
 
 
+def test_multidroplet_forces_spread_and_tiles_match_oracle_at_full_size():
+    # the 512 x 512 x 256 box with 16 droplets after 20 steps, on the GPU's
+    # own node positions: every droplet's nodal forces, the spread force
+    # field over all 67 M cells, and the stamped band tiles (bit-exact)
+    say("multidroplet full size")
+    import paper_2604_17463_amd as P
+    wl = configs.multidroplet_c5()
+    box = wl.boxes[0]
+    shape = (box.nz, box.ny, box.nx)
+    s = sim(wl, F32, flags=GRAPH)
+    s.step(20)
+    Fo, tw, qs, phi_sum, phi_abs = None, np.zeros(3), [], np.zeros(3), 0.0
+    for k, d in enumerate(wl.droplets):
+        qg = s.read_nodes(k)
+        A = oracle.wetting_A(d.sigma, d.theta_eq, d.xi, d.n_exp, d.m_exp)
+        want = oracle.node_forces(d.tris, qg, d.sigma, A, d.xi, d.n_exp, d.m_exp, d.k_vol,
+                                  oracle.volume(d.tris, d.nodes))["phi"]
+        got = s.compute_forces(k)
+        assert np.abs(got - want).max() < 2e-5 * np.abs(want).max(), k
+        Fo, t = oracle.spread(shape, box.zbc, qg, got, F=Fo)
+        tw += t
+        qs.append(qg)
+        phi_sum += got.sum(0)
+        phi_abs += np.abs(got).sum()
+    F, flags = s.compute_spread(0)
+    assert rel_l2(F, Fo) < 1e-6
+    assert np.array_equal(flags, oracle.touched_tiles(np.concatenate(qs), shape, box.zbc, tile=P.band_tile()))
+    assert np.allclose(F.sum(axis=(1, 2, 3)) + tw, phi_sum, rtol=0, atol=1e-7 * phi_abs)
+    s.close()
+
+
 def test_spreading_step_matches_oracle_from_gpu_state(perm):
     # sampled parity at full size: the oracle advances the GPU's own state
     # (populations and nodes after 200 steps) by one step; the GPU's next
