@@ -419,6 +419,32 @@ def test_multidroplet_forces_spread_and_tiles_match_oracle_at_full_size():
     s.close()
 
 
+def test_batched_forces_spread_and_tiles_match_oracle_at_full_size():
+    # the 64-box batched workload (28 M cells) after 20 steps, on the GPU's
+    # own node positions: per droplet its nodal forces, per box the spread
+    # force field and the stamped band tiles (bit-exact)
+    say("batched full size")
+    import paper_2604_17463_amd as P
+    wl = configs.batched_c4()
+    s = sim(wl, F32, flags=GRAPH)
+    s.step(20)
+    tile = P.band_tile()
+    for k, d in enumerate(wl.droplets):
+        box = wl.boxes[d.box]
+        shape = (box.nz, box.ny, box.nx)
+        qg = s.read_nodes(k)
+        A = oracle.wetting_A(d.sigma, d.theta_eq, d.xi, d.n_exp, d.m_exp)
+        want = oracle.node_forces(d.tris, qg, d.sigma, A, d.xi, d.n_exp, d.m_exp, d.k_vol,
+                                  oracle.volume(d.tris, d.nodes))["phi"]
+        got = s.compute_forces(k)
+        assert np.abs(got - want).max() < 2e-5 * np.abs(want).max(), k
+        F, flags = s.compute_spread(d.box)
+        Fo, tw = oracle.spread(shape, box.zbc, qg, got)
+        assert rel_l2(F, Fo) < 1e-6, k
+        assert np.array_equal(flags, oracle.touched_tiles(qg, shape, box.zbc, tile=tile)), k
+    s.close()
+
+
 def test_spreading_step_matches_oracle_from_gpu_state(perm):
     # sampled parity at full size: the oracle advances the GPU's own state
     # (populations and nodes after 200 steps) by one step; the GPU's next
