@@ -60,3 +60,52 @@ def test_spreading_trace_fp32_matches_the_oracle_every_100_steps():
     sim.close()
     for k, (e, st) in worst.items():
         assert e <= TOL[k], f"{k}: {e:.3e} at step {st} > {TOL[k]:.0e}"
+
+
+# Reduced-precision storage of the deviations (FP16 scaled by 4096, BF16) on
+# the same trace.  Measured worst relative errors over the 20,000 steps:
+#   FP16  height 1.6e-5, contact radius 9.5e-6, volume 1.4e-5, mass 6.4e-7
+#   BF16  height 3.2e-3, contact radius 9.0e-4, volume 1.4e-4, mass 2.5e-6
+# (BF16 keeps 8 significant bits of each deviation).  The bounds are about
+# three times these: regression bounds for the storage formats, reported
+# against the FP64 oracle as the method's own error.
+TOL_LOWP = {
+    "f16dev": {"height": 5e-5, "contact_radius": 3e-5, "volume": 5e-5, "mass": 2e-6},
+    "bf16dev": {"height": 1e-2, "contact_radius": 3e-3, "volume": 5e-4, "mass": 1e-5},
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["f16dev", "bf16dev"])
+def test_spreading_trace_reduced_precision_matches_the_oracle(name):
+    import paper_2604_17463_amd as P
+    from iblb_inputs import configs
+    from make_spreading_trace import workload_hash
+
+    with open(os.path.join(HERE, "golden", "spreading_trace_oracle.json")) as fh:
+        tr = json.load(fh)
+    wl = configs.spreading_c2(steps=tr["steps"])
+    assert tr["workload_sha256"] == workload_hash(wl), "stored trace is of another workload"
+    storage, scale = (P.IBLB_F16DEV, 4096.0) if name == "f16dev" else (P.IBLB_BF16DEV, 1.0)
+    say(f"spreading trace: {name}, graph + autotune, 20k steps")
+    sim = P.Simulation(wl, storage=storage, flags=P.IBLB_FLAG_GRAPH | P.IBLB_FLAG_AUTOTUNE,
+                       dev_scale=scale)
+    tol = TOL_LOWP[name]
+    worst = {k: (0.0, 0) for k in tol}
+    done = 0
+    for row in tr["rows"]:
+        if row["step"] > done:
+            sim.step(row["step"] - done)
+            done = row["step"]
+        drops, boxes = sim.observables()
+        d, b = drops[0], boxes[0]
+        got = {"height": d["height"], "contact_radius": d["contact_radius"],
+               "volume": d["volume"], "mass": b["mass"]}
+        for k in tol:
+            e = abs(got[k] - row[k]) / abs(row[k])
+            if e > worst[k][0]:
+                worst[k] = (e, row["step"])
+    say("worst relative errors (error, step): " + json.dumps(worst))
+    sim.close()
+    for k, (e, st) in worst.items():
+        assert e <= tol[k], f"{name} {k}: {e:.3e} at step {st} > {tol[k]:.0e}"
