@@ -4,6 +4,10 @@
     rocprofv3 --pmc WRITE_SIZE -d OUT -- python -m paper_2604_17463_amd.profiling
     rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2604_17463_amd.profiling
 
+With --steps WORKLOAD N it instead runs N graph-replayed, autotuned FP32
+steps of a named workload (spreading, batched or multidroplet) after 20
+warm-up steps and prints the step time, for kernel traces of whole steps.
+
 First a plain device copy of a known size (torch's copy kernel) serves as
 the calibration of the memory counters, then the bulk kernel runs 3 + `reps`
 times in a fixed launch shape on the 128x128x64 spreading workload and on a
@@ -25,8 +29,12 @@ def main():
                          "bulk launch on the spreading workload")
     ap.add_argument("--launch-box", type=int, nargs=5, default=(256, 1, 1, 1, 0),
                     help="the same on the 256x256x128 box")
+    ap.add_argument("--steps", nargs=2, metavar=("WORKLOAD", "N"),
+                    help="run N steps of spreading, batched or multidroplet instead")
     args = ap.parse_args()
     import torch
+    if args.steps:
+        return run_steps(args.steps[0], int(args.steps[1]))
 
     import paper_2604_17463_amd as P
     from iblb_inputs import configs
@@ -50,6 +58,27 @@ def main():
                      "launch": list(sim.get_launch())}
         sim.close()
     print(json.dumps(res), flush=True)
+
+
+def run_steps(name, n):
+    import time
+
+    import torch
+
+    import paper_2604_17463_amd as P
+    from iblb_inputs import configs
+    wl = {"spreading": configs.spreading_c2, "batched": configs.batched_c4,
+          "multidroplet": configs.multidroplet_c5}[name]()
+    sim = P.Simulation(wl, storage=P.IBLB_F32, flags=P.IBLB_FLAG_GRAPH | P.IBLB_FLAG_AUTOTUNE)
+    sim.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(n)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"workload": wl.name, "cells": wl.cells, "steps": n, "ms_per_step": dt / n * 1e3,
+                      "launch": list(sim.get_launch())}), flush=True)
+    sim.close()
 
 
 if __name__ == "__main__":
