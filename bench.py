@@ -276,11 +276,14 @@ def paper_spreading(taus, n_tmu):
         every = max(1, int(round(tmu / 2)))
         n = int(round(2 * n_tmu))
         rows, dt = [], 0.0
-        for _ in range(n):
+        for i in range(1, n + 1):
             dt += timed_steps(sim, every)
             d, _ = sim.observables()
             rows.append([round(d[0]["step"] / tmu, 3), round(d[0]["height"] / r0, 5),
                          round(math.degrees(d[0]["theta_app"]), 3)])
+            if i % 20 == 0:
+                print(f"paper spreading tau {tau}: t/t_mu {rows[-1][0]:.1f} h/R0 {rows[-1][1]:.4f}",
+                      file=sys.stderr, flush=True)
         sim.close()
         out[f"tau{tau:g}"] = {"workload": wl.name, "re": wl.extra["re"], "t_mu": tmu,
                               "steps": every * n, "mlups": round(wl.cells * every * n / dt / 1e6, 1),
