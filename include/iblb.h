@@ -175,17 +175,33 @@ iblb_status iblb_velocity_set(int32_t *c, double *w);
  * call).  Fails with IBLB_E_INVAL / IBLB_E_MESH on an invalid configuration. */
 iblb_status iblb_workspace_size(const iblb_config *cfg, size_t *bytes);
 
-/* Validate the configuration, lay out the workspace, upload meshes and
- * tables, set the fluid at rest (f = w rho0) and compute each droplet's
- * reference volume V0.  `dev_workspace` must be device memory of at least
- * iblb_workspace_size bytes, 256-byte aligned.  `hip_stream` is a
- * hipStream_t (NULL = default stream).  Synchronising. */
+/* Set up the problem of Sec. 2: the lattice boxes (D3Q19 BGK fluid with
+ * relaxation time tau, Eqs. 1-6, walls as halfway bounce-back) and the
+ * closed droplet meshes with fixed connectivity that the fluid carries.
+ * Validates the configuration, lays out the workspace, uploads meshes and
+ * tables, sets the fluid at rest (f_i = w_i rho0, the equilibrium of Eq. 3
+ * at u = 0), computes each droplet's wetting amplitude
+ * A = sigma (m-1)(n-1)(1 + cos theta_eq) / ((n-m) xi) (Eq. 11) and its
+ * reference volume V0 (the FP64 mesh volume of the initial positions, used
+ * by the optional volume penalty; not in the paper).  `dev_workspace` must
+ * be device memory of at least iblb_workspace_size bytes, 256-byte aligned,
+ * owned by the caller.  `hip_stream` is a hipStream_t (NULL = default
+ * stream).  On success *out owns the context (free it with iblb_destroy);
+ * on failure *out is NULL and iblb_last_error(NULL) holds the message.
+ * Synchronising. */
 iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
                       void *hip_stream, struct iblb_ctx **out);
 
-/* Enqueue n_steps full time steps t -> t+1 (forces at q^t, spreading, fused
- * stream-collide, interpolation of u^t at q^t, forward Euler advection).
- * Asynchronous.  Returns IBLB_E_STATE after an instability was reported. */
+/* Enqueue n_steps full time steps t -> t+1 of Sec. 2, in this order:
+ * nodal forces at q^t (surface tension from the area gradient, the wetting
+ * force -chi Pi(d) n / 3 with Pi of Eq. 10; Eqs. 9-11), spreading of those
+ * forces onto the lattice with the 4-point delta (Eq. 8), the fused
+ * stream-collide with the Guo source (Eqs. 1-6, u^t including the
+ * half-force term), interpolation of u^t at q^t (Eq. 7) and the forward
+ * Euler advection q^{t+1} = q^t + U.  n_steps >= 0 (0 is a no-op).
+ * Asynchronous: only enqueues on the context's stream.  Returns
+ * IBLB_E_INVAL for n_steps < 0, IBLB_E_STATE after an instability was
+ * reported by iblb_observables, IBLB_E_DEVICE when a launch fails. */
 iblb_status iblb_step(struct iblb_ctx *ctx, int64_t n_steps);
 
 /* Observables of the current state (per droplet and per box).  Either

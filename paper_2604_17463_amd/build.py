@@ -18,11 +18,6 @@ FLAGS = [
 ]
 
 
-MEMBENCH = os.path.join(HERE, "membench")
-MEMBENCH_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-Wall",
-                  "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-
-
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = ["hipcc", *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
@@ -31,13 +26,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    # the memory-system probe used for the bandwidth ceiling
-    tmp = MEMBENCH + ".tmp"
-    cmd = ["hipcc", *MEMBENCH_FLAGS, "-o", tmp, os.path.join(HERE, "csrc", "membench.hip")]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, MEMBENCH)
     return LIB
 
 

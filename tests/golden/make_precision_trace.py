@@ -1,7 +1,7 @@
 """Write the FP64 oracle's observable trace of the 256x256x128 precision
 workload (one 40,962-node sphere of radius 48 relaxing toward 45 degrees)
-for tau = 0.6 and tau = 1.0, every 500 steps up to 2,000 steps.  Calls only
-the oracle and the input generators.
+for tau = 0.6 and tau = 1.0, every 500 steps up to the workload's configured
+10,000 steps.  Calls only the oracle and the input generators.
 
     python tests/golden/make_precision_trace.py [steps] [every]
 """
@@ -44,7 +44,7 @@ def trace(tau, steps, every):
 
 
 def main():
-    steps = int(sys.argv[1]) if len(sys.argv) > 1 else 2000
+    steps = int(sys.argv[1]) if len(sys.argv) > 1 else 10000
     every = int(sys.argv[2]) if len(sys.argv) > 2 else 500
     for tau in (0.6, 1.0):
         out = trace(tau, steps, every)

@@ -195,3 +195,41 @@ def test_shear_wave_decay_gives_paper_viscosities():
         assert abs(nu - mu_printed) <= max(tol, 2e-3 * mu_printed), (tau, nu, mu_printed)
     sigma, R0, mu, re_printed, tol = re_row
     assert abs(sigma * R0 / mu ** 2 - re_printed) < tol
+
+
+def _first_order_populations(rho, u):
+    """f_i = w_i rho (1 + 3 c_i . u) per cell: by the lattice isotropy
+    (sum w c = 0, sum w c c = I/3) its density is rho and its momentum rho u
+    exactly, independently of the oracle's equilibrium."""
+    rho = np.asarray(rho, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    cu = np.einsum("ia,a...->i...", C.astype(np.float64), u)
+    return W.reshape((19,) + (1,) * rho.ndim) * rho[None] * (1.0 + 3.0 * cu)
+
+
+def test_max_u_of_a_uniform_field_is_its_velocity():
+    # every cell carries the same (rho, U): max |sum c f| / rho = |U|
+    shape = (3, 4, 5)
+    U = np.array([0.03, -0.04, 0.012])
+    rho = np.full(shape, 1.07)
+    f = _first_order_populations(rho, np.broadcast_to(U[:, None, None, None], (3,) + shape))
+    assert abs(oracle.max_u(f) - np.linalg.norm(U)) < 1e-15
+
+
+def test_max_u_takes_the_largest_cell_and_divides_by_the_local_density():
+    # two regions of different density and velocity; the largest speed sits
+    # in the light region.  Dividing by a reference density instead of the
+    # cell's own, or dropping a velocity component, picks the other region
+    # or another value.
+    shape = (4, 4, 6)
+    rho = np.full(shape, 2.0)
+    u = np.zeros((3,) + shape)
+    u[0] = 0.05                                  # heavy region: |u| = 0.05, |j| = 0.1
+    light = (slice(None), slice(None), slice(3, 5))
+    rho[light] = 0.5
+    u[:, light[0], light[1], light[2]] = np.array([0.02, -0.03, 0.06])[:, None, None, None]
+    u[:, 1, 2, 4] = [0.0, 0.0, -0.071]           # one cell of the light region is the fastest
+    f = _first_order_populations(rho, u)
+    assert abs(oracle.max_u(f) - 0.071) < 1e-15
+    # a fluid at rest has no velocity at any density
+    assert oracle.max_u(_first_order_populations(rho, np.zeros_like(u))) == 0.0
