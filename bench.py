@@ -2,22 +2,32 @@
 
 A step is one full time step of the hot path (triangle and node forces,
 spreading, fused stream-collide, interpolation and advection), replayed as
-hipGraphs.  The headline workload is the spreading run: a 128x128x64 box
-(1,048,576 cells) with one 10,242-node droplet relaxing from a 150 degree
-cap toward 60 degrees, FP32 population storage.  One JSON line is printed;
-besides the headline it carries:
-  - the observable error of the FP32 run against the stored FP64 oracle
-    trace of the same run (tests/golden/spreading_trace_oracle.json);
-  - the same run with FP16- and BF16-deviation storage (speed and error);
-  - the bulk stream-collide kernel on an HBM-resident 256x256x128 box;
+hipGraphs.  The headline workload is the largest single-GPU configuration:
+a 512x512x256 box (67,108,864 cells, 10.2 GB of FP32 populations per
+buffer pair) with 16 droplets of 10,242 nodes each on a 4x4 grid over the
+wetting wall, FP32 population storage.  One JSON line is printed; besides
+the headline it carries:
+  - the roofline of the dominant kernel (the fused stream-collide over every
+    cell, timed with HIP events on the library's stream in the step's launch
+    shape) and the step-level fraction of HBM peak;
+  - the same box with FP16-deviation storage against FP32 over the
+    configured 5,000 steps (speed-up, worst observable error);
+  - the 128x128x64 spreading run (cache-resident: its two population
+    buffers fit in the 256 MB last-level cache) in FP32, FP16- and
+    BF16-deviation storage, with observable errors against the stored FP64
+    oracle trace (tests/golden/spreading_trace_oracle.json);
+  - the bulk stream-collide kernel alone on an HBM-resident 256x256x128 box;
   - the 256x256x128 precision workload (40,962-node droplet, tau 0.6 and
-    1.0) in FP64, FP32, FP16- and BF16-deviation storage, with observable
-    errors against the stored FP64 oracle trace and against the FP64 run;
-  - the 512x512x256 box with 16 droplets in FP32 and FP16-deviation storage;
-  - the 64-box batched workload in one context against 64 sequential runs;
-  - the FP64 oracle timed on the host cores (cpu_baseline);
-  - with --paper-spreading, the paper's own spreading runs at their scale
-    (h / R0 against t / t_mu for the given tau values).
+    1.0) in FP64, FP32, FP16- and BF16-deviation storage over its configured
+    10,000 steps, with observable errors against the stored FP64 oracle trace
+    and against the FP64 run;
+  - the 64-box batched workload in one context, FP32 and FP16-deviation,
+    against 64 sequential FP32 contexts;
+  - the FP64 oracle timed on the host cores on the headline workload
+    (cpu_baseline);
+  - opt-in: the paper's own spreading runs at their scale (--paper-spreading),
+    the two wetting runs of Sec. 4 (--paper-sec4), and the free droplet in
+    shear at the paper's parameters (--paper-shear).
 """
 from __future__ import annotations
 
@@ -71,7 +81,8 @@ def rel_errors(got, ref, keys=OBS):
 
 
 def bulk_rate(sim, cells, storage, reps=50):
-    """Bulk kernel alone, in the context's launch configuration: (ms, GB/s)."""
+    """Bulk kernel alone over every cell, in the context's launch shape:
+    (ms, GB/s of algorithmic traffic)."""
     sim.time_stream_collide(reps=3)
     ms = sim.time_stream_collide(reps=reps)
     return ms, cells * cell_bytes(storage) / (ms * 1e-3) / 1e9
@@ -86,21 +97,35 @@ def timed_steps(sim, steps):
     return time.perf_counter() - t0
 
 
-def oracle_errors(drop, box, step):
-    """Relative error of the GPU observables against the stored oracle trace
-    at the same step (None when the trace is absent or does not reach it)."""
+def band_cells(sim, b=0):
+    """Cells of the band tiles the node pass stamps at the current state."""
+    _, flags = sim.compute_spread(b, want_F=False)
+    return int(flags.sum()) * 64
+
+
+def oracle_errors(sim):
+    """Advance the spreading run to the next row of the stored oracle trace
+    (rows every 100 steps) and return the relative error of the observables
+    there, with the step used; None when the trace is absent or ends
+    earlier."""
     if not os.path.exists(TRACE):
         return None
     with open(TRACE) as fh:
         tr = json.load(fh)
     rows = {r["step"]: r for r in tr["rows"]}
-    if step not in rows:
+    d, _ = sim.observables()
+    now = d[0]["step"]
+    target = min((s for s in rows if s >= now), default=None)
+    if target is None:
         return None
-    r = rows[step]
-    out = {"step": step}
+    if target > now:
+        sim.step(target - now)
+    d, b = sim.observables()
+    r = rows[target]
+    out = {"step": target}
     for k in ("height", "contact_radius", "volume", "area"):
-        out[k] = abs(drop[k] - r[k]) / abs(r[k])
-    out["mass"] = abs(box["mass"] - r["mass"]) / r["mass"]
+        out[k] = abs(d[0][k] - r[k]) / abs(r[k])
+    out["mass"] = abs(b[0]["mass"] - r["mass"]) / r["mass"]
     return out
 
 
@@ -118,74 +143,87 @@ def traffic_record():
 
 def cpu_baseline(wl, seconds: float):
     """The oracle on the host cores (all the process may use, then one
-    thread), on the same workload from its initial state."""
+    thread), on the same workload from its initial state: steps until
+    `seconds` have passed, then one step on one thread."""
     import oracle
     cores = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        cores = min(cores, int(os.environ["OMP_NUM_THREADS"]))
     oracle.set_threads(cores)
-
-    def rate(limit):
-        sim = oracle.OracleSim(wl)
-        sim.step(1)  # first touch of the arrays outside the timing
-        t0 = time.perf_counter()
-        n = 0
-        while True:
-            sim.step(1)
-            n += 1
-            dt = time.perf_counter() - t0
-            if dt >= limit or n >= 10000:
-                return n, dt
-
-    n, dt = rate(seconds)
+    sim = oracle.OracleSim(wl)
+    sim.step(1)  # first touch of the arrays outside the timing
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        sim.step(1)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            break
     used = oracle.num_threads()
     oracle.set_threads(1)
-    n1, dt1 = rate(seconds / 3)
+    t1 = time.perf_counter()
+    sim.step(1)
+    dt1 = time.perf_counter() - t1
     oracle.set_threads(cores)
     return {"value": round(wl.cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": used,
-            "kind": "oracle", "value_1_thread": round(wl.cells * n1 / dt1 / 1e6, 3),
-            "sample": f"{n} steps of the {wl.name} workload after its first step "
-                      f"({dt:.1f} s, FP64, OpenMP over z-slabs on {used} threads); "
-                      f"one thread: {n1} steps in {dt1:.1f} s"}
+            "kind": "oracle", "value_1_thread": round(wl.cells / dt1 / 1e6, 3),
+            "sample": f"{n} steps of the {wl.name} workload ({wl.cells:,} cells, {wl.nodes:,} IB "
+                      f"nodes) after its first step ({dt:.1f} s, FP64, OpenMP over z-slabs on "
+                      f"{used} threads); one thread: 1 step in {dt1:.1f} s"}
 
 
-def run_spreading(storage, warmup, steps, autotune=True):
+def spreading_variants(args):
+    """The 128x128x64 spreading run (cache-resident) in three storages."""
     from iblb_inputs import configs
-    wl = configs.spreading_c2()
-    sim = make_sim(wl, storage, autotune)
-    sim.step(warmup)
-    dt = timed_steps(sim, steps)
-    drops, boxes = sim.observables()
-    return wl, sim, dt, drops[0], boxes[0]
-
-
-def variants(args, f32_drop, total_steps):
-    from iblb_inputs import configs
-    from iblb_inputs.configs import Box, Workload
     out = {}
-    # reduced-precision population storage on the same spreading run
-    for st in ("f16dev", "bf16dev"):
-        wl, sim, dt, d, b = run_spreading(st, args.warmup, args.steps)
-        k1 = sim.time_stream_collide(reps=100)
-        out[st] = {"mlups": round(wl.cells * args.steps / dt / 1e6, 3),
-                   "ms_per_step": dt / args.steps * 1e3,
-                   "bulk_kernel_ms": k1,
-                   "bulk_GBs": round(wl.cells * cell_bytes(st) / (k1 * 1e-3) / 1e9, 1),
-                   "rel_err_vs_f32": {k: abs(d[k] - f32_drop[k]) / abs(f32_drop[k])
-                                      for k in ("height", "contact_radius", "volume")},
-                   "rel_err_vs_oracle": oracle_errors(d, b, total_steps)}
+    f32 = None
+    for st in ("f32", "f16dev", "bf16dev"):
+        wl = configs.spreading_c2()
+        sim = make_sim(wl, st)
+        sim.step(args.spreading_warmup)
+        dt = timed_steps(sim, args.spreading_steps)
+        d, _ = sim.observables()
+        k1, gbs = bulk_rate(sim, wl.cells, st, reps=100)
+        r = {"workload": wl.name, "cache_resident": True,
+             "mlups": round(wl.cells * args.spreading_steps / dt / 1e6, 3),
+             "ib_nodes_per_s": wl.nodes * args.spreading_steps / dt,
+             "ms_per_step": dt / args.spreading_steps * 1e3,
+             "bulk_kernel_ms": k1, "bulk_GBs_cache_resident": round(gbs, 1),
+             "launch": list(sim.get_launch())}
+        if st == "f32":
+            r["mesh_kernels_ms"] = sim.time_mesh_chain(reps=100)
+            f32 = d[0]
+        else:
+            r["rel_err_vs_f32"] = {k: abs(d[0][k] - f32[k]) / abs(f32[k])
+                                   for k in ("height", "contact_radius", "volume")}
+            r["speedup_vs_f32"] = out["f32"]["ms_per_step"] / r["ms_per_step"]
+        r["rel_err_vs_oracle"] = oracle_errors(sim)
         sim.close()
-    # HBM-resident box (1.3 GB of FP32 populations, beyond the 256 MB cache)
+        out[st] = r
+    return out
+
+
+def hbm_box():
+    from iblb_inputs.configs import Box, Workload
     big = Workload("box-256x256x128", [Box(256, 256, 128, tau=0.6)], [])
+    out = {}
     for st in ("f32", "f16dev"):
         sim = make_sim(big, st)
-        sim.time_stream_collide(reps=5)
-        k1 = sim.time_stream_collide(reps=50)
-        gbs = big.cells * cell_bytes(st) / (k1 * 1e-3) / 1e9
-        out[f"hbm_box_{st}"] = {"workload": big.name, "bulk_kernel_ms": k1,
-                                "mlups": round(big.cells / (k1 * 1e-3) / 1e6, 1),
-                                "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                "launch": list(sim.get_launch())}
+        k1, gbs = bulk_rate(sim, big.cells, st)
+        out[st] = {"workload": big.name, "bulk_kernel_ms": k1,
+                   "mlups": round(big.cells / (k1 * 1e-3) / 1e6, 1),
+                   "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                   "launch": list(sim.get_launch())}
         sim.close()
-    # precision workload: FP64 / FP32 / FP16 / BF16 storage on the same run
+    return out
+
+
+def precision(args):
+    """FP64 / FP32 / FP16 / BF16 storage on the precision workload over its
+    configured length, against the stored oracle trace and the FP64 run."""
+    from iblb_inputs import configs
+    out = {}
     for tau in (0.6, 1.0):
         wl = configs.precision_c3(tau=tau, steps=args.precision_steps)
         ref_path = PTRACE.format(tau=tau)
@@ -213,54 +251,80 @@ def variants(args, f32_drop, total_steps):
             if oracle_row is not None:
                 r["rel_err_vs_oracle"] = rel_errors(r["obs"], oracle_row, OBS + ("mass",))
             r["speedup_vs_f32"] = runs["f32"]["ms_per_step"] / r["ms_per_step"]
-        out[f"precision_tau{tau:g}"] = {"workload": wl.name, "steps": args.precision_steps,
-                                         "oracle_trace": oracle_row is not None, "runs": runs}
-    # the 512x512x256 box with 16 droplets: FP32 against FP16-deviation storage
-    if not args.no_large:
-        wl = configs.multidroplet_c5()
-        runs = {}
-        for st in ("f32", "f16dev"):
-            sim = make_sim(wl, st)
-            sim.step(20)
-            dt = timed_steps(sim, args.large_steps)
+        out[f"tau{tau:g}"] = {"workload": wl.name, "steps": args.precision_steps,
+                              "oracle_trace": oracle_row is not None, "runs": runs}
+    return out
+
+
+def large_precision(args):
+    """The headline box in FP32 and FP16-deviation storage over the configured
+    length; the worst relative difference of each droplet observable,
+    sampled every `every` steps."""
+    from iblb_inputs import configs
+    wl = configs.multidroplet_c5()
+    n, every = args.large_steps, max(1, args.large_steps // 10)
+    runs, trace = {}, {}
+    for st in ("f32", "f16dev"):
+        sim = make_sim(wl, st)
+        sim.step(20)
+        dt, rows = 0.0, []
+        done = 0
+        while done < n:
+            k = min(every, n - done)
+            dt += timed_steps(sim, k)
+            done += k
             drops, boxes = sim.observables()
-            ms, gbs = bulk_rate(sim, wl.cells, st, reps=20)
-            runs[st] = {"mlups": round(wl.cells * args.large_steps / dt / 1e6, 1),
-                        "ib_nodes_per_s": wl.nodes * args.large_steps / dt,
-                        "ms_per_step": dt / args.large_steps * 1e3, "bulk_GBs": round(gbs, 1),
-                        "bulk_frac": round(gbs / HBM_PEAK_GBS, 4), "launch": list(sim.get_launch()),
-                        "drops": [{k: d[k] for k in OBS} for d in drops], "mass": boxes[0]["mass"]}
-            sim.close()
-        worst = {k: max(abs(a[k] - b[k]) / abs(b[k]) for a, b in zip(runs["f16dev"]["drops"], runs["f32"]["drops"]))
-                 for k in OBS}
-        for r in runs.values():
-            r.pop("drops")
-        out["large_multidroplet"] = {"workload": wl.name, "cells": wl.cells, "ib_nodes": wl.nodes,
-                                     "steps": args.large_steps, "runs": runs,
-                                     "f16dev_worst_rel_err_vs_f32": worst,
-                                     "f16dev_speedup_vs_f32": runs["f32"]["ms_per_step"] / runs["f16dev"]["ms_per_step"]}
-    # batched: 64 uneven boxes in one context vs 64 sequential contexts
-    if not args.no_batched:
-        wl = configs.batched_c4()
-        nb_steps = args.batched_steps
-        sim = make_sim(wl, "f32")
+            rows.append(([{key: d[key] for key in OBS} for d in drops], boxes[0]["mass"]))
+        ms, gbs = bulk_rate(sim, wl.cells, st, reps=20)
+        runs[st] = {"mlups": round(wl.cells * n / dt / 1e6, 1), "ib_nodes_per_s": wl.nodes * n / dt,
+                    "ms_per_step": dt / n * 1e3, "bulk_GBs": round(gbs, 1),
+                    "bulk_frac": round(gbs / HBM_PEAK_GBS, 4), "launch": list(sim.get_launch())}
+        trace[st] = rows
+        sim.close()
+    worst = {k: max(abs(a[k] - b[k]) / abs(b[k])
+                    for (da, _), (db, _) in zip(trace["f16dev"], trace["f32"]) for a, b in zip(da, db))
+             for k in OBS}
+    worst["mass"] = max(abs(ma - mb) / mb for (_, ma), (_, mb) in zip(trace["f16dev"], trace["f32"]))
+    return {"workload": wl.name, "cells": wl.cells, "ib_nodes": wl.nodes, "steps": n + 20,
+            "compared_every": every, "runs": runs, "f16dev_worst_rel_err_vs_f32": worst,
+            "f16dev_speedup_vs_f32": runs["f32"]["ms_per_step"] / runs["f16dev"]["ms_per_step"]}
+
+
+def batched(args):
+    """64 uneven boxes in one context (FP32 and FP16-deviation) against 64
+    sequential FP32 contexts; the FP16 run's worst observable error against
+    the FP32 batch."""
+    from iblb_inputs import configs
+    from iblb_inputs.configs import Workload
+    wl = configs.batched_c4()
+    nb_steps = args.batched_steps
+    res, obs = {}, {}
+    for st in ("f32", "f16dev"):
+        sim = make_sim(wl, st)
         sim.step(20)
         dt = timed_steps(sim, nb_steps)
+        drops, boxes = sim.observables()
+        obs[st] = ([{k: d[k] for k in OBS} for d in drops], [b["mass"] for b in boxes])
+        res[st] = {"mlups": round(wl.cells * nb_steps / dt / 1e6, 3),
+                   "ib_nodes_per_s": wl.nodes * nb_steps / dt, "ms_per_step": dt / nb_steps * 1e3,
+                   "launch": list(sim.get_launch())}
         sim.close()
-        seq_time = 0.0
-        for k in range(len(wl.boxes)):
-            one = Workload("one", [wl.boxes[k]], [replace(wl.droplets[k], box=0)], storage=1)
-            s = make_sim(one, "f32")
-            s.step(20)
-            seq_time += timed_steps(s, nb_steps)
-            s.close()
-        out["batched"] = {"workload": wl.name, "boxes": len(wl.boxes), "cells": wl.cells,
-                          "ib_nodes": wl.nodes, "steps": nb_steps,
-                          "mlups": round(wl.cells * nb_steps / dt / 1e6, 3),
-                          "ib_nodes_per_s": wl.nodes * nb_steps / dt,
-                          "sequential_mlups": round(wl.cells * nb_steps / seq_time / 1e6, 3),
-                          "speedup_vs_sequential": seq_time / dt}
-    return out
+    seq_time = 0.0
+    for k in range(len(wl.boxes)):
+        one = Workload("one", [wl.boxes[k]], [replace(wl.droplets[k], box=0)], storage=1)
+        s = make_sim(one, "f32")
+        s.step(20)
+        seq_time += timed_steps(s, nb_steps)
+        s.close()
+    worst = {k: max(abs(a[k] - b[k]) / abs(b[k]) for a, b in zip(obs["f16dev"][0], obs["f32"][0]))
+             for k in OBS}
+    worst["mass"] = max(abs(a - b) / b for a, b in zip(obs["f16dev"][1], obs["f32"][1]))
+    return {"workload": wl.name, "boxes": len(wl.boxes), "cells": wl.cells, "ib_nodes": wl.nodes,
+            "steps": nb_steps, "runs": res,
+            "sequential_f32_mlups": round(wl.cells * nb_steps / seq_time / 1e6, 3),
+            "speedup_vs_sequential": seq_time / nb_steps * 1e3 / res["f32"]["ms_per_step"],
+            "f16dev_worst_rel_err_vs_f32": worst,
+            "f16dev_speedup_vs_f32": res["f32"]["ms_per_step"] / res["f16dev"]["ms_per_step"]}
 
 
 def paper_spreading(taus, n_tmu):
@@ -392,16 +456,22 @@ def paper_shear(n_cap):
             "t_over_tcap_d_over_dinf_inclination_deg": rows}
 
 
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=sorted(STORAGE))
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--spreading-steps", type=int, default=5000)
+    ap.add_argument("--spreading-warmup", type=int, default=200)
     ap.add_argument("--batched-steps", type=int, default=1000)
-    ap.add_argument("--precision-steps", type=int, default=2000)
-    ap.add_argument("--large-steps", type=int, default=500)
+    ap.add_argument("--precision-steps", type=int, default=10000)
+    ap.add_argument("--large-steps", type=int, default=5000)
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -425,59 +495,74 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    wl, sim, dt, drop, box = run_spreading(args.storage, args.warmup, args.steps,
-                                           not args.no_autotune)
+    from iblb_inputs import configs
+    wl = configs.multidroplet_c5()
+    progress(f"headline {wl.name}: init and autotune")
+    sim = make_sim(wl, args.storage, not args.no_autotune)
+    sim.step(args.warmup)
+    progress(f"headline: {args.steps} timed steps")
+    dt = timed_steps(sim, args.steps)
+    drops, boxes = sim.observables()
     cells, nodes = wl.cells, wl.nodes
     mlups = cells * args.steps / dt / 1e6
-    # dominant kernel: the bulk stream-collide, timed alone with HIP events
-    # on the library's stream in the launch shape the timed steps used
-    _, flags = sim.compute_spread(0)
-    band = int(flags.sum()) * 64
-    k1_ms = sim.time_stream_collide(reps=200)
+    band = sum(band_cells(sim, b) for b in range(len(wl.boxes)))
+    # dominant kernel: the bulk stream-collide over every cell, timed alone
+    # with HIP events on the library's stream in the launch shape of the
+    # timed steps
+    k1_ms = sim.time_stream_collide(reps=3)
+    k1_ms = sim.time_stream_collide(reps=50)
     # the mesh kernels alone (nodes/s over their time, without the fluid)
-    mesh_ms = sim.time_mesh_chain(reps=200)
+    mesh_ms = sim.time_mesh_chain(reps=20)
     bytes_k1 = cells * cell_bytes(args.storage)
     achieved = bytes_k1 / (k1_ms * 1e-3) / 1e9
     launch = sim.get_launch()
-    # the same kernel without the grid cap the step uses to leave CU slots to
-    # the concurrent mesh kernels
-    sim.set_launch(*launch[:4], 0)
-    k1_free_ms = sim.time_stream_collide(reps=200)
     sim.close()
     tr = traffic_record()
     traffic = None
     if (tr and tr.get("workload") == wl.name and tr.get("storage") == args.storage
-            and tuple(tr.get("launch", ())) == tuple(launch)):
+            and tuple(tr.get("launch", ()))[:4] == tuple(launch)[:4]):
         traffic = tr["hbm_bytes_per_launch"]
+    step_bytes = bytes_k1 + band * BYTES_PER_BAND_CELL + nodes * BYTES_PER_NODE
     out = {
         "metric": METRIC, "value": round(mlups, 3), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.storage == "f64" else "f32", "data": "synthetic",
-        "config": {"workload": wl.name, "cells": cells, "ib_nodes": nodes,
-                   "storage": args.storage, "graph": True, "bulk_launch": list(launch)},
+        "config": {"workload": wl.name, "cells": cells, "ib_nodes": nodes, "droplets": len(wl.droplets),
+                   "storage": args.storage, "graph": True, "launch": list(launch)},
         "ib_nodes_per_s": nodes * args.steps / dt,
         "ib_nodes_per_s_mesh_kernels": nodes / (mesh_ms * 1e-3),
         "mesh_kernels_ms": mesh_ms,
         "bytes_per_cell_update": cell_bytes(args.storage),
-        "step_roofline_frac": (bytes_k1 + band * BYTES_PER_BAND_CELL + nodes * BYTES_PER_NODE)
-        * args.steps / dt
-        / (HBM_PEAK_GBS * 1e9),
+        "step_bytes": step_bytes,
+        "step_roofline_frac": step_bytes * args.steps / dt / (HBM_PEAK_GBS * 1e9),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_bulk (fused pull-stream/collide, every cell)",
+                     "kernel": "k_bulk (fused pull-stream/BGK-Guo collide over every cell; in the step it "
+                               "skips the band tiles, which the band kernel computes beside it)",
                      "kernel_ms": k1_ms, "bytes_per_launch": bytes_k1, "band_cells": band,
-                     "launch": list(launch),
-                     "uncapped": {"kernel_ms": k1_free_ms,
-                                  "achieved": round(bytes_k1 / (k1_free_ms * 1e-3) / 1e9, 1),
-                                  "frac": round(bytes_k1 / (k1_free_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
-        "observables": {"step": drop["step"], "height": drop["height"],
-                        "contact_radius": drop["contact_radius"], "volume": drop["volume"],
-                        "mass": box["mass"]},
-        "rel_err_vs_oracle": oracle_errors(drop, box, args.warmup + args.steps),
+                     "launch": list(launch)},
+        "observables": {"step": drops[0]["step"], "mass": boxes[0]["mass"],
+                        "height_mean": sum(d["height"] for d in drops) / len(drops),
+                        "volume_total": sum(d["volume"] for d in drops)},
+        "rel_err_vs_oracle": None,
+        "parity": "tests/test_gpu_window.py: one step on windows of this box against the oracle",
     }
     if not args.no_variants:
-        out["variants"] = variants(args, drop, args.warmup + args.steps)
+        v = {}
+        progress("spreading run (cache-resident) in three storages")
+        v["spreading"] = spreading_variants(args)
+        progress("bulk kernel on the HBM-resident 256x256x128 box")
+        v["hbm_box"] = hbm_box()
+        progress(f"precision workload, {args.precision_steps} steps in four storages")
+        v["precision"] = precision(args)
+        if not args.no_large:
+            progress(f"headline box FP32 vs FP16, {args.large_steps} steps")
+            v["large_fp16"] = large_precision(args)
+        if not args.no_batched:
+            progress("batched 64 boxes vs sequential")
+            v["batched"] = batched(args)
+        out["variants"] = v
     if args.paper_spreading:
         out["paper_spreading"] = paper_spreading(
             [float(t) for t in args.paper_spreading.split(",")], args.paper_tmu)
@@ -486,8 +571,8 @@ def main():
     if args.paper_shear > 0:
         out["paper_shear"] = paper_shear(args.paper_shear)
     if not args.no_cpu_baseline:
-        from iblb_inputs import configs
-        out["cpu_baseline"] = cpu_baseline(configs.spreading_c2(), args.cpu_seconds)
+        progress("oracle on the host cores")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -69,7 +69,13 @@ enum { IBLB_Z_WALLS = 0, IBLB_Z_PERIODIC = 1 };
 /* iblb_config.flags */
 enum {
     IBLB_FLAG_GRAPH = 1u,    /* replay each step as a captured hipGraph      */
-    IBLB_FLAG_AUTOTUNE = 2u, /* time the stream-collide launch shapes at init */
+    IBLB_FLAG_AUTOTUNE = 2u, /* time the stream-collide launch shapes and the
+                                step schedule at init (iblb_set_launch); the
+                                result is kept for later inits of the same
+                                device, storage, boxes and droplet sizes in
+                                the process, and across processes in the
+                                file named by the environment variable
+                                IBLB_TUNE_CACHE, if set                     */
     IBLB_FLAG_FULL_U = 4u    /* write u of every cell each step (testing);
                                 otherwise only cells near a mesh            */
 };
@@ -79,11 +85,10 @@ enum {
     IBLB_BIT_RHO = 1u,        /* a density was non-finite or <= 0         */
     IBLB_BIT_MACH = 2u,       /* |u| exceeded the lattice sound speed     */
     IBLB_BIT_WALL = 4u,       /* a node reached d <= 0 (Pi is singular)   */
-    IBLB_BIT_JUMP = 8u,       /* a node moved more than 1 lu in one step  */
-    IBLB_BIT_BAND = 16u       /* with tau_in: a cell went inside or outside
-                                 away from every node's stencil (triangles
-                                 too large for the mesh's node spacing);
-                                 its relaxation time lagged one step      */
+    IBLB_BIT_JUMP = 8u,       /* a node moved more than 1 lu in one step,
+                                 or a coordinate left |q| < 1e7            */
+    IBLB_BIT_BAND = 16u       /* reserved, never set: every cell relaxes
+                                 with the inside bits of its own step      */
 };
 
 typedef struct {
@@ -217,6 +222,16 @@ iblb_status iblb_observables(struct iblb_ctx *ctx, iblb_obs *per_droplet, int32_
  * Synchronising. */
 iblb_status iblb_read_state(struct iblb_ctx *ctx, int32_t box, double *f_out, double *u_out);
 
+/* The same for a window of box `box`: the cells lo[0] .. lo[0]+ext[0]-1
+ * along x and lo[1] .. lo[1]+ext[1]-1 along y, both taken modulo the box
+ * size (a window may cross the periodic sides), and lo[2] .. lo[2]+ext[2]-1
+ * along z (inside [0, nz) in a walled box, modulo nz in a z-periodic one);
+ * 1 <= ext[a] <= the box size.  f_out [19][ext2][ext1][ext0], u_out (may be
+ * NULL) [3][ext2][ext1][ext0], as iblb_read_state gives them; only the rows
+ * the window needs are copied from the device.  Synchronising. */
+iblb_status iblb_read_window(struct iblb_ctx *ctx, int32_t box, const int32_t *lo, const int32_t *ext,
+                             double *f_out, double *u_out);
+
 /* Replace the populations of box `box` by f_in (layout as iblb_read_state),
  * converted to the storage precision.  Synchronising. */
 iblb_status iblb_write_state(struct iblb_ctx *ctx, int32_t box, const double *f_in);
@@ -270,7 +285,8 @@ iblb_status iblb_state_size(const struct iblb_ctx *ctx, size_t *bytes);
 iblb_status iblb_save_state(struct iblb_ctx *ctx, void *blob, size_t bytes);
 iblb_status iblb_load_state(struct iblb_ctx *ctx, const void *blob, size_t bytes);
 
-/* Launch configuration of the fused stream-collide kernel:
+/* Launch configuration of the fused stream-collide kernel and the step
+ * schedule:
  *   threads_x         threads along x per row, a multiple of 32;
  *   rows_per_group    rows of a workgroup; threads_x * rows_per_group must be
  *                     a multiple of 64 and at most 256;
@@ -281,15 +297,21 @@ iblb_status iblb_load_state(struct iblb_ctx *ctx, const void *blob, size_t bytes
  *                     last-level cache, hurts while they fit);
  *   max_workgroups    0, or a cap on the grid: the workgroups then loop over
  *                     the rows, leaving compute units to the mesh kernels that
- *                     run beside the stream-collide.
+ *                     run beside the stream-collide;
+ *   band_after_bulk   0: the cells of the band tiles (those within reach of a
+ *                     node's stencil) are computed by the band kernel beside
+ *                     the stream-collide of the other cells, which waits for
+ *                     the step's node pass; 1: the stream-collide runs over
+ *                     every cell beside the mesh kernels and the band kernel
+ *                     then recomputes the band tiles (not with tau_in).
  * Other values return IBLB_E_INVAL.  Rebuilds the step graphs.  Synchronising.
  * Results do not depend on the configuration. */
 iblb_status iblb_set_launch(struct iblb_ctx *ctx, int32_t threads_x, int32_t rows_per_group,
                             int32_t cells_per_thread, int32_t streaming_stores,
-                            int32_t max_workgroups);
+                            int32_t max_workgroups, int32_t band_after_bulk);
 iblb_status iblb_get_launch(const struct iblb_ctx *ctx, int32_t *threads_x, int32_t *rows_per_group,
                             int32_t *cells_per_thread, int32_t *streaming_stores,
-                            int32_t *max_workgroups);
+                            int32_t *max_workgroups, int32_t *band_after_bulk);
 
 /* Shape of the band tiles that iblb_compute_spread's tile_flags refer to:
  * shape[0..2] = cells per tile along x, y, z (a tile is 64 cells).  Tiles are

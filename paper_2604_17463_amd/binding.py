@@ -21,7 +21,7 @@ IBLB_BIT_RHO, IBLB_BIT_MACH, IBLB_BIT_WALL, IBLB_BIT_JUMP, IBLB_BIT_BAND = 1, 2,
 
 EXPORTS = (
     "iblb_velocity_set", "iblb_workspace_size", "iblb_init", "iblb_step", "iblb_observables",
-    "iblb_read_state", "iblb_write_state", "iblb_read_nodes", "iblb_write_nodes",
+    "iblb_read_state", "iblb_read_window", "iblb_write_state", "iblb_read_nodes", "iblb_write_nodes",
     "iblb_compute_forces", "iblb_compute_spread", "iblb_interpolate", "iblb_read_bins",
     "iblb_read_csr", "iblb_read_inside", "iblb_state_size", "iblb_save_state", "iblb_load_state",
     "iblb_set_launch", "iblb_time_mesh_chain", "iblb_get_launch", "iblb_band_tile", "iblb_time_stream_collide",
@@ -86,6 +86,7 @@ def load():
     L.iblb_step.argtypes = [vp, i64]
     L.iblb_observables.argtypes = [vp, C.POINTER(iblb_obs), i32, C.POINTER(iblb_box_obs), i32]
     L.iblb_read_state.argtypes = [vp, i32, dp, dp]
+    L.iblb_read_window.argtypes = [vp, i32, ip, ip, dp, dp]
     L.iblb_write_state.argtypes = [vp, i32, dp]
     L.iblb_read_nodes.argtypes = [vp, i32, dp]
     L.iblb_write_nodes.argtypes = [vp, i32, dp]
@@ -99,8 +100,8 @@ def load():
     L.iblb_time_mesh_chain.argtypes = [vp, i32, C.POINTER(C.c_double)]
     L.iblb_save_state.argtypes = [vp, vp, C.c_size_t]
     L.iblb_load_state.argtypes = [vp, vp, C.c_size_t]
-    L.iblb_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
-    L.iblb_get_launch.argtypes = [vp, ip, ip, ip, ip, ip]
+    L.iblb_set_launch.argtypes = [vp, i32, i32, i32, i32, i32, i32]
+    L.iblb_get_launch.argtypes = [vp, ip, ip, ip, ip, ip, ip]
     L.iblb_band_tile.argtypes = [ip]
     L.iblb_time_stream_collide.argtypes = [vp, i32, dp]
     L.iblb_destroy.argtypes = [vp]
@@ -245,6 +246,17 @@ class Simulation:
         self._chk(load().iblb_read_state(self.ctx, b, _dptr(f), _dptr(u) if want_u else None))
         return (f, u) if want_u else f
 
+    def read_window(self, lo, ext, b=0, want_u=False):
+        """Populations (and velocity) of the cells lo + [0, ext) of box b,
+        periodic sides wrapped; f [19][ez][ey][ex]."""
+        lo3 = (C.c_int32 * 3)(*[int(v) for v in lo])
+        ext3 = (C.c_int32 * 3)(*[int(v) for v in ext])
+        ex, ey, ez = (int(v) for v in ext)
+        f = np.empty((19, ez, ey, ex))
+        u = np.empty((3, ez, ey, ex)) if want_u else None
+        self._chk(load().iblb_read_window(self.ctx, b, lo3, ext3, _dptr(f), _dptr(u) if want_u else None))
+        return (f, u) if want_u else f
+
     def write_state(self, f, b=0):
         f = np.ascontiguousarray(f, dtype=np.float64)
         self._chk(load().iblb_write_state(self.ctx, b, _dptr(f)))
@@ -263,12 +275,14 @@ class Simulation:
         self._chk(load().iblb_compute_forces(self.ctx, d, _dptr(phi)))
         return phi
 
-    def compute_spread(self, b=0):
+    def compute_spread(self, b=0, want_F=True):
+        """Spread force density of box b ([3][nz][ny][nx], or None without
+        want_F) and the flags of the band tiles holding a stencil cell."""
         nz, ny, nx = self._box(b)
-        F = np.empty((3, nz, ny, nx))
+        F = np.empty((3, nz, ny, nx)) if want_F else None
         tx, ty, tz = band_tile()
         flags = np.zeros((-(-nz // tz), -(-ny // ty), -(-nx // tx)), np.uint8)
-        self._chk(load().iblb_compute_spread(self.ctx, b, _dptr(F),
+        self._chk(load().iblb_compute_spread(self.ctx, b, _dptr(F) if want_F else None,
                                              flags.ctypes.data_as(C.POINTER(C.c_uint8))))
         return F, flags
 
@@ -310,14 +324,16 @@ class Simulation:
         self._chk(load().iblb_read_inside(self.ctx, b, m.ctypes.data_as(C.POINTER(C.c_uint8))))
         return m
 
-    def set_launch(self, threads_x, rows, cells_per_thread=1, streaming_stores=0, max_workgroups=0):
+    def set_launch(self, threads_x, rows, cells_per_thread=1, streaming_stores=0, max_workgroups=0,
+                   band_after_bulk=0):
         self._chk(load().iblb_set_launch(self.ctx, int(threads_x), int(rows), int(cells_per_thread),
-                                         int(streaming_stores), int(max_workgroups)))
+                                         int(streaming_stores), int(max_workgroups),
+                                         int(band_after_bulk)))
 
     def get_launch(self):
         """(threads_x, rows_per_group, cells_per_thread, streaming_stores,
-        max_workgroups) of the bulk kernel."""
-        v = [C.c_int32() for _ in range(5)]
+        max_workgroups, band_after_bulk) of the bulk kernel and the step."""
+        v = [C.c_int32() for _ in range(6)]
         self._chk(load().iblb_get_launch(self.ctx, *[C.byref(x) for x in v]))
         return tuple(x.value for x in v)
 

@@ -13,6 +13,10 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in ("iblb_fluid.hip", "iblb_mesh.
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Wall", "-Wno-unused-result",
+    # contract a*b+c into an FMA only within one expression, as written: the
+    # arithmetic of a cell must not depend on which template instantiation
+    # (launch shape) computes it
+    "-ffp-contract=on",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -8,8 +8,12 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <mutex>
 #include <numeric>
+#include <sstream>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -43,7 +47,7 @@ struct BoxHost {
     int sx = 0, tnx = 0, tny = 0, tnz = 0, n_tiles = 0, tile_base = 0;
     int64_t plane = 0;
     int blk_begin = 0, blk_end = 0;
-    size_t off_f[2] = {0, 0}, off_stamp = 0, off_F = 0, off_u = 0, off_ufull = 0;
+    size_t off_f[2] = {0, 0}, off_stamp[2] = {0, 0}, off_F = 0, off_u = 0, off_ufull = 0;
     size_t off_mask[2] = {0, 0};
     int nzw = 0;  // 64-bit mask words per column (boxes with tau_in)
 };
@@ -62,7 +66,8 @@ struct Plan {
            off_trec = 0, off_tile_list = 0, off_tile_count = 0, off_part = 0, off_breg = 0,
            off_base = 0, off_s0 = 0, off_bbox = 0, off_blk_drop = 0, off_tri = 0,
            off_csr_off = 0, off_csr_ent = 0, off_chunks = 0, off_tri_part = 0, off_rows = 0,
-           off_tchunk = 0, off_tcand = 0, off_tncand = 0, off_scan = 0, off_ctr = 0, off_status = 0, off_obs_part = 0, off_obs_out = 0,
+           off_tchunk = 0, off_tcand = 0, off_tncand = 0, off_scan = 0, off_ctr = 0, off_step_epoch = 0, off_status = 0, off_obs_part = 0,
+           off_obs_out = 0,
            off_uout = 0, total = 0;
 };
 
@@ -298,7 +303,7 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
     };
     for (auto &H : p.boxes) {
         for (int k = 0; k < 2; ++k) H.off_f[k] = take((size_t)Q * H.plane * eb, BIG_ALIGN);
-        H.off_stamp = take((size_t)H.n_tiles * 4);
+        for (int k = 0; k < 2; ++k) H.off_stamp[k] = take((size_t)H.n_tiles * 4);
         H.off_F = take((size_t)H.n_tiles * 3 * TILE_CELLS * p.real);
         H.off_u = take((size_t)H.n_tiles * 3 * TILE_CELLS * p.real);
         if (p.flags & IBLB_FLAG_FULL_U) H.off_ufull = take((size_t)3 * H.plane * p.real);
@@ -334,6 +339,7 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
     p.off_tncand = take((size_t)2 * p.total_tiles * 4);
     p.off_scan = take((size_t)2 * p.boxes.size() * 4);
     p.off_ctr = take(4);
+    p.off_step_epoch = take(2 * 4);
     p.off_status = take(4);
     p.off_obs_part = take(2 * (size_t)OBS_GROUPS * 8);
     p.off_obs_out = take(((size_t)p.drops.size() * OBS_DROP + p.boxes.size() * OBS_BOX) * 8);
@@ -364,6 +370,8 @@ struct iblb_ctx {
     bool u_valid = false;    // the full u field holds the last step's velocity
     int32_t epoch = 0;       // host mirror of the device step epoch
     int32_t last_step_epoch = -1;
+    int last_step_parity = 0;  // buffer parity of the last step (its stamp set)
+    hipEvent_t ev_chain = nullptr, ev_bulk = nullptr;  // joins inside a run of steps
     bool unstable = false;
     std::string err = "no error";
     double *host_obs = nullptr;
@@ -413,37 +421,74 @@ iblb_status compute_masks(iblb_ctx *c, int slot, hipStream_t s) {
     return IBLB_OK;
 }
 
-// One time step on stream s.  The bulk stream-collide (every cell, body
-// force only) runs on s while the mesh chain runs on the second stream:
-// [advection of the previous step] -> triangle records -> node pass (forces,
-// weights, stamps, partial spread) -> stamped-tile list.  Both join before
-// the band kernel, which gathers the spread force of every stamped tile and
-// redoes the collision of its cells.  The advection of this step is left
-// pending (it only needs this step's band velocities) and runs first in the
-// next step's mesh chain, or in flush().
-iblb_status enqueue_step(iblb_ctx *c, hipStream_t s, int parity, bool advect_first) {
+// n consecutive time steps on stream s, the first with buffer parity
+// `parity`.  Per step, on the second stream, the mesh chain: [advection of
+// the previous step] -> inside bits -> triangle records -> node pass
+// (forces, weights, tile stamps, partial spread) -> stamped-tile list.  The
+// band kernel gathers the spread force of every stamped tile and does the
+// collision of its cells; the bulk stream-collide does the collision of the
+// other cells with the body force only.  Two schedules (Launch::after),
+// chosen by the autotuner; every cell gets the same arithmetic in both:
+//   0 (band beside bulk): the bulk kernel of step k runs on s after the
+//     node pass of step k (its stamps and inside bits) and skips the stamped
+//     tiles; the band kernel runs on the second stream right after the node
+//     pass, once the bulk kernel of step k-1 is done (it overwrites the
+//     buffer that kernel read).  The mesh chain of step k+1 follows the band
+//     kernel on the second stream, beside the bulk kernel of step k: per
+//     step, one queue crossing each way.
+//   1 (band after bulk): the bulk kernel of step k runs over every cell on
+//     s beside the mesh chain of step k, which forks from s after the band
+//     kernel of step k-1; the band kernel then overwrites its tiles on s,
+//     after both.  The bulk kernel relaxes with the previous step's inside
+//     bits, so this schedule is not used with a viscosity contrast.
+// The advection of the last step is left pending (it only needs that step's
+// band velocities) and runs first in the next chain, or in flush().  A run
+// ends joined into s.
+iblb_status enqueue_steps(iblb_ctx *c, hipStream_t s, int parity, bool advect_first, int n) {
     const bool f64 = is_f64(c);
     const int full_u = (c->plan.flags & IBLB_FLAG_FULL_U) ? 1 : 0;
     const float scale = (float)c->plan.scale;
     if (c->plan.nblk == 0) {
-        HIPCHK(c, launch_bulk(c->P, c->plan.storage, parity, full_u, scale, c->L, s));
+        for (int k = 0; k < n; ++k)
+            HIPCHK(c, launch_bulk(c->P, c->plan.storage, parity ^ (k & 1), full_u, scale, c->L, false, s));
+        return IBLB_OK;
+    }
+    auto chain = [&](int k, int p) -> iblb_status {
+        if (advect_first || k > 0) HIPCHK(c, launch_interp(c->P, f64, 0, nullptr, c->ib));
+        const iblb_status st = compute_masks(c, p, c->ib);
+        if (st != IBLB_OK) return st;
+        HIPCHK(c, launch_tri(c->P, f64, c->ib));
+        HIPCHK(c, launch_node(c->P, f64, 0, p, c->ib));
+        HIPCHK(c, hipEventRecord(c->ev_chain, c->ib));
+        return IBLB_OK;
+    };
+    if (c->L.after) {
+        for (int k = 0; k < n; ++k) {
+            const int p = parity ^ (k & 1);
+            HIPCHK(c, hipEventRecord(c->ev_fork, s));
+            HIPCHK(c, hipStreamWaitEvent(c->ib, c->ev_fork, 0));
+            const iblb_status st = chain(k, p);
+            if (st != IBLB_OK) return st;
+            HIPCHK(c, launch_bulk(c->P, c->plan.storage, p, full_u, scale, c->L, false, s));
+            HIPCHK(c, hipStreamWaitEvent(s, c->ev_chain, 0));
+            HIPCHK(c, launch_band(c->P, c->plan.storage, p, full_u, scale, true, s));
+        }
         return IBLB_OK;
     }
     HIPCHK(c, hipEventRecord(c->ev_fork, s));
     HIPCHK(c, hipStreamWaitEvent(c->ib, c->ev_fork, 0));
-    if (advect_first) HIPCHK(c, launch_interp(c->P, f64, 0, nullptr, c->ib));
-    {
-        // this step's inside bits (the bulk kernel reads the other set)
-        const iblb_status st = compute_masks(c, parity, c->ib);
+    for (int k = 0; k < n; ++k) {
+        const int p = parity ^ (k & 1);
+        const iblb_status st = chain(k, p);
         if (st != IBLB_OK) return st;
+        HIPCHK(c, hipStreamWaitEvent(s, c->ev_chain, 0));
+        HIPCHK(c, launch_bulk(c->P, c->plan.storage, p, full_u, scale, c->L, true, s));
+        if (k > 0) HIPCHK(c, hipStreamWaitEvent(c->ib, c->ev_bulk, 0));  // the previous step's bulk kernel
+        HIPCHK(c, launch_band(c->P, c->plan.storage, p, full_u, scale, true, c->ib));
+        HIPCHK(c, hipEventRecord(c->ev_bulk, s));
     }
-    HIPCHK(c, launch_tri(c->P, f64, c->ib));
-    HIPCHK(c, launch_node(c->P, f64, 0, c->ib));
-    HIPCHK(c, launch_mask_check(c->P, parity, c->ib));
     HIPCHK(c, hipEventRecord(c->ev_join, c->ib));
-    HIPCHK(c, launch_bulk(c->P, c->plan.storage, parity, full_u, scale, c->L, s));
     HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
-    HIPCHK(c, launch_band(c->P, c->plan.storage, parity, full_u, scale, true, s));
     return IBLB_OK;
 }
 
@@ -479,7 +524,7 @@ iblb_status build_graphs(iblb_ctx *c) {
         for (int a = 0; a < 2; ++a) {
             hipGraph_t g = nullptr;
             HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-            iblb_status st = enqueue_step(c, c->capture, p, a == 1);
+            iblb_status st = enqueue_steps(c, c->capture, p, a == 1, 1);
             hipError_t e = hipStreamEndCapture(c->capture, &g);
             if (st != IBLB_OK) {
                 if (g) (void)hipGraphDestroy(g);
@@ -496,8 +541,7 @@ iblb_status build_graphs(iblb_ctx *c) {
     for (int p = 0; p < 2; ++p) {
         hipGraph_t g = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-        iblb_status st = IBLB_OK;
-        for (int k = 0; k < MULTI && st == IBLB_OK; ++k) st = enqueue_step(c, c->capture, p ^ (k & 1), true);
+        const iblb_status st = enqueue_steps(c, c->capture, p, true, MULTI);
         hipError_t e = hipStreamEndCapture(c->capture, &g);
         if (st != IBLB_OK) {
             if (g) (void)hipGraphDestroy(g);
@@ -521,6 +565,7 @@ const char *launch_problem(const Launch &L) {
     if (L.cpt == 2 && L.bx % 64) return "cells_per_thread 2 needs threads_x a multiple of 64";
     if (L.nt != 0 && L.nt != 1) return "streaming_stores must be 0 or 1";
     if (L.maxg < 0) return "max_workgroups must be >= 0";
+    if (L.after != 0 && L.after != 1) return "band_after_bulk must be 0 or 1";
     return nullptr;
 }
 static_assert(K1_MAX_THREADS == 256, "launch_problem() states the bound");
@@ -543,7 +588,7 @@ iblb_status time_k1(iblb_ctx *c, int reps, double *ms) {
     HIPCHK(c, hipEventCreate(&ev.b));
     HIPCHK(c, hipEventRecord(ev.a, c->stream));
     for (int r = 0; r < reps; ++r) {
-        HIPCHK(c, launch_bulk(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, c->L,
+        HIPCHK(c, launch_bulk(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, c->L, false,
                               c->stream));
         c->parity ^= 1;
     }
@@ -634,7 +679,7 @@ iblb_status autotune(iblb_ctx *c) {
             if (bx > (int)round_up((size_t)nxmax, 32)) continue;
             for (int threads : {64, 128, K1_MAX_THREADS})
                 for (int cpt : {1, 2}) {
-                    const Launch L{bx, threads / bx, 0, nt, cpt, 0};
+                    const Launch L{bx, threads / bx, 0, nt, cpt, 0, 0};
                     if (L.by < 1 || launch_problem(L)) continue;
                     double ms = 0;
                     iblb_status st = timed(L, &ms);
@@ -645,37 +690,39 @@ iblb_status autotune(iblb_ctx *c) {
                     }
                 }
         }
-    // 2. with meshes present and the step replayed as graphs, a cap on the
-    //    bulk grid is judged by whole steps: the workgroups it does not take
-    //    leave CU slots to the mesh kernels that run beside it, at some cost
-    //    in bulk bandwidth.  Under a cap, two rows per thread keep more loads
-    //    in flight per wave, so both are tried.  Each candidate starts from
-    //    the initial state.
+    // 2. with meshes present and the step replayed as graphs, the schedule
+    //    and a cap on the bulk grid are judged by whole steps: the workgroups
+    //    the cap does not take leave CU slots to the mesh kernels that run
+    //    beside it, at some cost in bulk bandwidth.  Under a cap, two rows per
+    //    thread keep more loads in flight per wave, so both are tried.  Each
+    //    candidate starts from the initial state.
     if (c->plan.nblk > 0 && (c->plan.flags & IBLB_FLAG_GRAPH)) {
         const int cus = c->P.n_cus;
         const int wpg = best.bx * best.by / 64;  // waves per workgroup
         double sbest = 1e300;
         Launch chosen = best;
-        for (int waves_per_cu : {0, 16, 12, 8, 6})
-            for (int cpt : {1, 2}) {
-                Launch L = best;
-                L.cpt = cpt;
-                if (launch_problem(L)) continue;
-                L.maxg = waves_per_cu ? std::max(1, cus * waves_per_cu / wpg) : 0;
-                c->L = L;
-                iblb_status st = upload_rows(c);
-                if (st != IBLB_OK) return st;
-                if (L.maxg && c->L.grid >= c->P.n_rowgroups) continue;  // no cap at this size
-                double ms = 0;
-                st = reset_state(c);
-                if (st == IBLB_OK) st = build_graphs(c);
-                if (st == IBLB_OK) st = time_steps(c, &ms);
-                if (st != IBLB_OK) return st;
-                if (ms < sbest) {
-                    sbest = ms;
-                    chosen = L;
+        for (int after = 0; after < (c->P.contrast ? 1 : 2); ++after)
+            for (int waves_per_cu : {0, 16, 12, 8, 6})
+                for (int cpt : {1, 2}) {
+                    Launch L = best;
+                    L.cpt = cpt;
+                    L.after = after;
+                    if (launch_problem(L)) continue;
+                    L.maxg = waves_per_cu ? std::max(1, cus * waves_per_cu / wpg) : 0;
+                    c->L = L;
+                    iblb_status st = upload_rows(c);
+                    if (st != IBLB_OK) return st;
+                    if (L.maxg && c->L.grid >= c->P.n_rowgroups) continue;  // no cap at this size
+                    double ms = 0;
+                    st = reset_state(c);
+                    if (st == IBLB_OK) st = build_graphs(c);
+                    if (st == IBLB_OK) st = time_steps(c, &ms);
+                    if (st != IBLB_OK) return st;
+                    if (ms < sbest) {
+                        sbest = ms;
+                        chosen = L;
+                    }
                 }
-            }
         best = chosen;
         iblb_status st = reset_state(c);
         if (st != IBLB_OK) return st;
@@ -691,6 +738,71 @@ iblb_status autotune(iblb_ctx *c) {
                                      (size_t)Q * H.plane * elem_bytes(c->plan.storage), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return IBLB_OK;
+}
+
+// ---- autotune results kept across contexts ----
+// Key: the device (architecture, compute units), storage, graph use,
+// viscosity contrast and moving walls, and per box its dimensions, z
+// boundary and the node count of its droplets -- what the timed candidates
+// depend on.  Kept per process, and in the text file that the environment
+// variable IBLB_TUNE_CACHE names (one "key<TAB>launch" line per entry;
+// later lines win), so that repeated inits of one configuration time once.
+std::mutex g_tune_mu;
+std::unordered_map<std::string, Launch> g_tune;
+
+iblb_status tune_key(iblb_ctx *c, std::string *key) {
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(c, hipGetDeviceProperties(&prop, dev));
+    std::ostringstream k;
+    k << prop.gcnArchName << "/cu" << c->P.n_cus << "/st" << c->plan.storage << "/g"
+      << ((c->plan.flags & IBLB_FLAG_GRAPH) ? 1 : 0) << "/c" << c->P.contrast << "/m" << c->P.moving;
+    for (size_t b = 0; b < c->plan.boxes.size(); ++b) {
+        const iblb_box &B = c->plan.boxes[b].b;
+        long nodes = 0;
+        for (const DropHost &d : c->plan.drops)
+            if (d.d.box == (int)b) nodes += d.d.n_nodes;
+        k << "/" << B.nx << "x" << B.ny << "x" << B.nz << "z" << B.zbc << "n" << nodes;
+    }
+    *key = k.str();
+    return IBLB_OK;
+}
+
+bool tune_lookup(const std::string &key, Launch *L) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+        *L = it->second;
+        return true;
+    }
+    const char *path = std::getenv("IBLB_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::ifstream in(path);
+    std::string line;
+    bool found = false;
+    while (std::getline(in, line)) {
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos || line.compare(0, tab, key) != 0 || tab != key.size()) continue;
+        std::istringstream v(line.substr(tab + 1));
+        Launch t{};
+        if (v >> t.bx >> t.by >> t.cpt >> t.nt >> t.maxg >> t.after) {
+            *L = t;
+            found = true;
+        }
+    }
+    if (found) g_tune[key] = *L;
+    return found;
+}
+
+void tune_store(const std::string &key, const Launch &L) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = L;
+    const char *path = std::getenv("IBLB_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream out(path, std::ios::app);
+    out << key << '\t' << L.bx << ' ' << L.by << ' ' << L.cpt << ' ' << L.nt << ' ' << L.maxg << ' ' << L.after
+        << '\n';
 }
 
 // ---- host conversion of stored populations (I/O only) ----
@@ -788,6 +900,7 @@ static iblb_status init_device(iblb_ctx *c) {
     P.tncand = (int32_t *)at(p.off_tncand);
     P.scan_all = (int32_t *)at(p.off_scan);
     P.ctr = (int32_t *)at(p.off_ctr);
+    P.step_epoch = (int32_t *)at(p.off_step_epoch);
     P.status = (uint32_t *)at(p.off_status);
     P.obs_part = (double *)at(p.off_obs_part);
     P.obs_out = (double *)at(p.off_obs_out);
@@ -827,7 +940,8 @@ static iblb_status init_device(iblb_ctx *c) {
         D.f[1] = at(H.off_f[1]);
         D.Fband = at(H.off_F);
         D.uband = at(H.off_u);
-        D.stamp = (int32_t *)at(H.off_stamp);
+        D.stamp[0] = (int32_t *)at(H.off_stamp[0]);
+        D.stamp[1] = (int32_t *)at(H.off_stamp[1]);
         D.ufull = (p.flags & IBLB_FLAG_FULL_U) ? at(H.off_ufull) : nullptr;
         D.tau = H.b.tau;
         D.rho0 = H.b.rho0;
@@ -935,13 +1049,16 @@ static iblb_status init_device(iblb_ctx *c) {
     for (auto &H : p.boxes) {
         for (int k = 0; k < 2; ++k)
             HIPCHK(c, hipMemsetAsync(at(H.off_f[k]), 0, (size_t)Q * H.plane * elem_bytes(p.storage), c->stream));
-        HIPCHK(c, hipMemsetAsync(at(H.off_stamp), 0xff, (size_t)H.n_tiles * 4, c->stream));
+        for (int k = 0; k < 2; ++k)
+            HIPCHK(c, hipMemsetAsync(at(H.off_stamp[k]), 0xff, (size_t)H.n_tiles * 4, c->stream));
         HIPCHK(c, hipMemsetAsync(at(H.off_F), 0, (size_t)H.n_tiles * 3 * TILE_CELLS * R, c->stream));
         HIPCHK(c, hipMemsetAsync(at(H.off_u), 0, (size_t)H.n_tiles * 3 * TILE_CELLS * R, c->stream));
         if (p.flags & IBLB_FLAG_FULL_U)
             HIPCHK(c, hipMemsetAsync(at(H.off_ufull), 0, (size_t)3 * H.plane * R, c->stream));
     }
     HIPCHK(c, hipMemsetAsync(P.ctr, 0, 4, c->stream));
+    // no epoch yet: 0xfefefefe matches neither an unstamped tile (-1) nor an epoch
+    HIPCHK(c, hipMemsetAsync(P.step_epoch, 0xfe, 8, c->stream));
     HIPCHK(c, hipMemsetAsync(P.tile_count, 0, 8, c->stream));
     HIPCHK(c, hipMemsetAsync(P.tncand, 0, (size_t)2 * p.total_tiles * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(P.scan_all, 0, (size_t)2 * p.boxes.size() * 4, c->stream));
@@ -968,7 +1085,19 @@ static iblb_status init_device(iblb_ctx *c) {
     c->L.cpt = 1;
     c->L.maxg = 0;
     st = upload_rows(c);
-    if (st == IBLB_OK && (p.flags & IBLB_FLAG_AUTOTUNE)) st = autotune(c);
+    if (st == IBLB_OK && (p.flags & IBLB_FLAG_AUTOTUNE)) {
+        std::string key;
+        Launch cached{};
+        st = tune_key(c, &key);
+        if (st == IBLB_OK && tune_lookup(key, &cached) && !launch_problem(cached) &&
+            !(cached.after && c->P.contrast)) {
+            c->L = cached;
+            st = upload_rows(c);
+        } else if (st == IBLB_OK) {
+            st = autotune(c);
+            if (st == IBLB_OK) tune_store(key, c->L);
+        }
+    }
     c->init_qh = std::vector<char>();
     c->init_ql = std::vector<char>();
     if (st == IBLB_OK) st = build_graphs(c);
@@ -1010,6 +1139,8 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
             what = "hipEventCreateWithFlags";
         }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_chain, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_bulk, hipEventDisableTiming);
         if (e != hipSuccess) {
             const std::string m = std::string(what) + ": " + hipGetErrorString(e);
             iblb_destroy(c);
@@ -1030,33 +1161,32 @@ iblb_status iblb_step(iblb_ctx *c, int64_t n) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
     if (n < 0) return set_err(c, IBLB_E_INVAL, "n_steps < 0");
     if (c->unstable) return set_err(c, IBLB_E_STATE, "context is unstable; no further steps");
-    for (int64_t k = 0; k < n; ++k) {
+    for (int64_t k = 0; k < n;) {
         const int a = c->pending ? 1 : 0;
-        if (a && n - k >= MULTI && c->multi[c->parity]) {
+        const int p0 = c->parity;
+        int64_t m = 1;
+        if (a && n - k >= MULTI && c->multi[p0]) {
             // MULTI steps, each starting with the previous step's advection
-            HIPCHK(c, hipGraphLaunch(c->multi[c->parity], c->stream));
-            c->parity ^= MULTI & 1;
-            c->step += MULTI;
-            c->u_valid = true;
-            c->epoch += MULTI;
-            c->last_step_epoch = c->epoch;
-            k += MULTI - 1;
-            continue;
-        }
-        if (c->exec[c->parity][a]) {
-            HIPCHK(c, hipGraphLaunch(c->exec[c->parity][a], c->stream));
+            HIPCHK(c, hipGraphLaunch(c->multi[p0], c->stream));
+            m = MULTI;
+        } else if (c->exec[p0][a]) {
+            HIPCHK(c, hipGraphLaunch(c->exec[p0][a], c->stream));
         } else {
-            iblb_status st = enqueue_step(c, c->stream, c->parity, a == 1);
+            // eager: up to 256 steps as one pipelined run
+            m = std::min<int64_t>(n - k, 256);
+            iblb_status st = enqueue_steps(c, c->stream, p0, a == 1, (int)m);
             if (st != IBLB_OK) return st;
         }
-        c->parity ^= 1;
-        ++c->step;
+        c->parity = p0 ^ (int)(m & 1);
+        c->step += m;
         c->u_valid = true;
         if (c->plan.nblk > 0) {
-            if (a) ++c->epoch;  // the advection at the head of the step
+            c->epoch += (int32_t)(m - 1 + a);  // one advection at the head of each step but the first
             c->last_step_epoch = c->epoch;
+            c->last_step_parity = p0 ^ (int)((m - 1) & 1);
             c->pending = true;
         }
+        k += m;
     }
     return IBLB_OK;
 }
@@ -1129,40 +1259,61 @@ double wall_term(const iblb_box &b, int i, bool lower) {
     return 6.0 * w_of(i) * b.rho0 * (cx_of(i) * u[0] + cy_of(i) * u[1]);
 }
 
-iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_out) {
+iblb_status iblb_read_window(iblb_ctx *c, int32_t box, const int32_t *lo, const int32_t *ext, double *f_out,
+                             double *u_out) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
-    if (box < 0 || box >= c->P.n_boxes || (!f_out && !u_out)) return set_err(c, IBLB_E_INVAL, "bad box or outputs");
+    if (box < 0 || box >= c->P.n_boxes || (!f_out && !u_out) || !lo || !ext)
+        return set_err(c, IBLB_E_INVAL, "bad box, window or outputs");
+    const BoxHost &H = c->plan.boxes[box];
+    const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz;
+    const bool zper = H.b.zbc == IBLB_Z_PERIODIC;
+    if (ext[0] < 1 || ext[1] < 1 || ext[2] < 1 || ext[0] > nx || ext[1] > ny || ext[2] > nz ||
+        (!zper && (lo[2] < 0 || lo[2] + ext[2] > nz)))
+        return set_err(c, IBLB_E_INVAL, "window outside the box (1 <= extent <= size; z inside a walled box)");
     {
         iblb_status fst = flush(c);
         if (fst != IBLB_OK) return fst;
     }
-    const BoxHost &H = c->plan.boxes[box];
-    const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz;
-    const size_t cells = (size_t)nx * ny * nz;
+    const int ex = ext[0], ey = ext[1], ez = ext[2];
+    const size_t wcells = (size_t)ex * ey * ez;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (f_out) {
+        // the planes' rows from one cell below the window to one above it
+        // (every row when a periodic window touches the z ends)
         const size_t eb = elem_bytes(c->plan.storage);
-        std::vector<char> raw((size_t)Q * H.plane * eb);
-        HIPCHK(c, hipMemcpy(raw.data(), c->ws + H.off_f[c->parity], raw.size(), hipMemcpyDeviceToHost));
-        const bool zper = H.b.zbc == IBLB_Z_PERIODIC;
-        for (int z = 0; z < nz; ++z)
-            for (int y = 0; y < ny; ++y)
-                for (int x = 0; x < nx; ++x) {
-                    const size_t cell = ((size_t)z * ny + y) * nx + x;
+        int za = lo[2] - 1, zb = lo[2] + ez;
+        if (zper && (za < 0 || zb >= nz)) {
+            za = 0;
+            zb = nz - 1;
+        }
+        za = std::max(za, 0);
+        zb = std::min(zb, nz - 1);
+        const size_t row = (size_t)H.sx * eb, slab = (size_t)(zb - za + 1) * ny * row;
+        std::vector<char> raw((size_t)Q * slab);
+        for (int i = 0; i < Q; ++i)
+            HIPCHK(c, hipMemcpy(raw.data() + (size_t)i * slab,
+                                c->ws + H.off_f[c->parity] + ((size_t)i * H.plane + (size_t)za * ny * H.sx) * eb, slab,
+                                hipMemcpyDeviceToHost));
+        const size_t pstride = slab / eb;  // elements per plane in raw
+        for (int wz = 0; wz < ez; ++wz)
+            for (int wy = 0; wy < ey; ++wy)
+                for (int wx = 0; wx < ex; ++wx) {
+                    const int z = zper ? wrap(lo[2] + wz, nz) : lo[2] + wz;
+                    const int y = wrap(lo[1] + wy, ny), x = wrap(lo[0] + wx, nx);
+                    const size_t cell = ((size_t)wz * ey + wy) * ex + wx;
                     for (int i = 0; i < Q; ++i) {
                         const int zs = z - cz_of(i);
                         size_t src;
                         double wall = 0.0;
                         if (!zper && (zs < 0 || zs >= nz)) {
-                            src = (size_t)opp_of(i) * H.plane + ((size_t)z * ny + y) * H.sx + x;
+                            src = (size_t)opp_of(i) * pstride + ((size_t)(z - za) * ny + y) * H.sx + x;
                             wall = wall_term(H.b, i, zs < 0);
                         } else {
-                            src = (size_t)i * H.plane +
-                                  ((size_t)wrap(zs, nz) * ny + wrap(y - cy_of(i), ny)) * H.sx +
+                            src = (size_t)i * pstride +
+                                  ((size_t)(wrap(zs, nz) - za) * ny + wrap(y - cy_of(i), ny)) * H.sx +
                                   wrap(x - cx_of(i), nx);
                         }
-                        f_out[(size_t)i * cells + cell] =
-                            w_of(i) * H.b.rho0 + (decode(c, raw.data(), src) + wall);
+                        f_out[(size_t)i * wcells + cell] = w_of(i) * H.b.rho0 + (decode(c, raw.data(), src) + wall);
                     }
                 }
     }
@@ -1171,34 +1322,45 @@ iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_o
         std::vector<char> uf((size_t)3 * H.plane * R);
         HIPCHK(c, hipMemcpy(uf.data(), c->ws + H.off_ufull, uf.size(), hipMemcpyDeviceToHost));
         for (int a = 0; a < 3; ++a)
-            for (int z = 0; z < nz; ++z)
-                for (int y = 0; y < ny; ++y)
-                    for (int x = 0; x < nx; ++x) {
+            for (int wz = 0; wz < ez; ++wz)
+                for (int wy = 0; wy < ey; ++wy)
+                    for (int wx = 0; wx < ex; ++wx) {
+                        const int z = wrap(lo[2] + wz, nz), y = wrap(lo[1] + wy, ny), x = wrap(lo[0] + wx, nx);
                         const size_t k = (size_t)a * H.plane + ((size_t)z * ny + y) * H.sx + x;
                         const double v = R == 8 ? ((double *)uf.data())[k] : ((float *)uf.data())[k];
-                        u_out[(size_t)a * cells + ((size_t)z * ny + y) * nx + x] = c->u_valid ? v : NAN;
+                        u_out[(size_t)a * wcells + ((size_t)wz * ey + wy) * ex + wx] = c->u_valid ? v : NAN;
                     }
     } else if (u_out) {
         const int R = c->plan.real;
         std::vector<char> ub((size_t)H.n_tiles * 3 * TILE_CELLS * R);
         std::vector<int32_t> stamp(H.n_tiles);
         HIPCHK(c, hipMemcpy(ub.data(), c->ws + H.off_u, ub.size(), hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(stamp.data(), c->ws + H.off_stamp, stamp.size() * 4, hipMemcpyDeviceToHost));
-        for (int z = 0; z < nz; ++z)
-            for (int y = 0; y < ny; ++y)
-                for (int x = 0; x < nx; ++x) {
-                    const size_t cell = ((size_t)z * ny + y) * nx + x;
+        HIPCHK(c, hipMemcpy(stamp.data(), c->ws + H.off_stamp[c->last_step_parity], stamp.size() * 4,
+                            hipMemcpyDeviceToHost));
+        for (int wz = 0; wz < ez; ++wz)
+            for (int wy = 0; wy < ey; ++wy)
+                for (int wx = 0; wx < ex; ++wx) {
+                    const int z = wrap(lo[2] + wz, nz), y = wrap(lo[1] + wy, ny), x = wrap(lo[0] + wx, nx);
+                    const size_t cell = ((size_t)wz * ey + wy) * ex + wx;
                     const size_t tile = (size_t)band_tile(x, y, z, H.tnx, H.tny);
                     const int loc = band_loc(x, y, z);
                     const bool ok = c->last_step_epoch >= 0 && stamp[tile] == c->last_step_epoch;
                     for (int a = 0; a < 3; ++a) {
                         const size_t k = (tile * 3 + a) * TILE_CELLS + loc;
                         const double v = R == 8 ? ((const double *)ub.data())[k] : ((const float *)ub.data())[k];
-                        u_out[(size_t)a * cells + cell] = ok ? v : NAN;
+                        u_out[(size_t)a * wcells + cell] = ok ? v : NAN;
                     }
                 }
     }
     return IBLB_OK;
+}
+
+iblb_status iblb_read_state(iblb_ctx *c, int32_t box, double *f_out, double *u_out) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (box < 0 || box >= c->P.n_boxes) return set_err(c, IBLB_E_INVAL, "bad box or outputs");
+    const iblb_box &B = c->plan.boxes[box].b;
+    const int32_t lo[3] = {0, 0, 0}, ext[3] = {B.nx, B.ny, B.nz};
+    return iblb_read_window(c, box, lo, ext, f_out, u_out);
 }
 
 iblb_status iblb_write_state(iblb_ctx *c, int32_t box, const double *f_in) {
@@ -1313,7 +1475,7 @@ iblb_status iblb_compute_forces(iblb_ctx *c, int32_t d, double *phi_out) {
     }
     const bool f64 = is_f64(c);
     HIPCHK(c, launch_tri(c->P, f64, c->stream));
-    HIPCHK(c, launch_node(c->P, f64, 1, c->stream));
+    HIPCHK(c, launch_node(c->P, f64, 1, c->parity, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const DropHost &H = c->plan.drops[d];
     const int N = c->P.Ntot, R = c->plan.real;
@@ -1337,7 +1499,7 @@ iblb_status iblb_compute_spread(iblb_ctx *c, int32_t b, double *F_out, uint8_t *
     }
     const bool f64 = is_f64(c);
     HIPCHK(c, launch_tri(c->P, f64, c->stream));
-    HIPCHK(c, launch_node(c->P, f64, 0, c->stream));
+    HIPCHK(c, launch_node(c->P, f64, 0, c->parity, c->stream));
     HIPCHK(c, launch_band(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, false, c->stream));
     HIPCHK(c, launch_epoch(c->P, c->stream));
     const int32_t used = c->epoch;
@@ -1345,10 +1507,10 @@ iblb_status iblb_compute_spread(iblb_ctx *c, int32_t b, double *F_out, uint8_t *
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const BoxHost &H = c->plan.boxes[b];
     const int R = c->plan.real;
-    std::vector<char> Fb((size_t)H.n_tiles * 3 * TILE_CELLS * R);
+    std::vector<char> Fb(F_out ? (size_t)H.n_tiles * 3 * TILE_CELLS * R : 0);
     std::vector<int32_t> stamp(H.n_tiles);
-    HIPCHK(c, hipMemcpy(Fb.data(), c->ws + H.off_F, Fb.size(), hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(stamp.data(), c->ws + H.off_stamp, stamp.size() * 4, hipMemcpyDeviceToHost));
+    if (F_out) HIPCHK(c, hipMemcpy(Fb.data(), c->ws + H.off_F, Fb.size(), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(stamp.data(), c->ws + H.off_stamp[c->parity], stamp.size() * 4, hipMemcpyDeviceToHost));
     const int nx = H.b.nx, ny = H.b.ny, nz = H.b.nz;
     const size_t cells = (size_t)nx * ny * nz;
     if (flags_out)
@@ -1398,7 +1560,7 @@ iblb_status iblb_interpolate(iblb_ctx *c, int32_t d, const double *u_in, double 
     const bool f64 = is_f64(c);
     double *Udev = (double *)(c->ws + c->plan.off_uout);
     HIPCHK(c, launch_tri(c->P, f64, c->stream));
-    HIPCHK(c, launch_node(c->P, f64, 1, c->stream));
+    HIPCHK(c, launch_node(c->P, f64, 1, c->parity, c->stream));
     HIPCHK(c, launch_interp(c->P, f64, 1, Udev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::vector<double> U((size_t)3 * c->P.Ntot);
@@ -1416,7 +1578,7 @@ iblb_status iblb_read_bins(iblb_ctx *c, int32_t d, int32_t *base_out) {
         if (fst != IBLB_OK) return fst;
     }
     HIPCHK(c, launch_tri(c->P, is_f64(c), c->stream));
-    HIPCHK(c, launch_node(c->P, is_f64(c), 1, c->stream));
+    HIPCHK(c, launch_node(c->P, is_f64(c), 1, c->parity, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const DropHost &H = c->plan.drops[d];
     const iblb_box &B = c->plan.boxes[H.d.box].b;
@@ -1644,10 +1806,13 @@ iblb_status iblb_read_csr(iblb_ctx *c, int32_t d, int32_t *offsets, int32_t *ent
     return IBLB_OK;
 }
 
-iblb_status iblb_set_launch(iblb_ctx *c, int32_t bx, int32_t by, int32_t cpt, int32_t nt, int32_t maxg) {
+iblb_status iblb_set_launch(iblb_ctx *c, int32_t bx, int32_t by, int32_t cpt, int32_t nt, int32_t maxg,
+                            int32_t after) {
     if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
-    const Launch L{bx, by, 0, nt, cpt, maxg};
+    const Launch L{bx, by, 0, nt, cpt, maxg, after};
     if (const char *why = launch_problem(L)) return set_err(c, IBLB_E_INVAL, why);
+    if (L.after && c->P.contrast)
+        return set_err(c, IBLB_E_INVAL, "band_after_bulk needs a configuration without tau_in");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->L = L;
     iblb_status st = upload_rows(c);
@@ -1656,13 +1821,14 @@ iblb_status iblb_set_launch(iblb_ctx *c, int32_t bx, int32_t by, int32_t cpt, in
 }
 
 iblb_status iblb_get_launch(const iblb_ctx *c, int32_t *bx, int32_t *by, int32_t *cpt, int32_t *nt,
-                            int32_t *maxg) {
-    if (!c || !bx || !by || !cpt || !nt || !maxg) return set_err(nullptr, IBLB_E_INVAL, "NULL argument");
+                            int32_t *maxg, int32_t *after) {
+    if (!c || !bx || !by || !cpt || !nt || !maxg || !after) return set_err(nullptr, IBLB_E_INVAL, "NULL argument");
     *bx = c->L.bx;
     *by = c->L.by;
     *cpt = c->L.cpt;
     *nt = c->L.nt;
     *maxg = c->L.maxg;
+    *after = c->L.after;
     return IBLB_OK;
 }
 
@@ -1704,8 +1870,7 @@ iblb_status iblb_time_mesh_chain(iblb_ctx *c, int32_t reps, double *ms) {
         iblb_status st = compute_masks(c, c->parity, c->stream);
         if (st != IBLB_OK) return st;
         HIPCHK(c, launch_tri(c->P, f64, c->stream));
-        HIPCHK(c, launch_node(c->P, f64, 0, c->stream));
-        HIPCHK(c, launch_mask_check(c->P, c->parity, c->stream));
+        HIPCHK(c, launch_node(c->P, f64, 0, c->parity, c->stream));
         HIPCHK(c, launch_interp(c->P, f64, 1, Udev, c->stream));
     }
     HIPCHK(c, hipEventRecord(ev.b, c->stream));
@@ -1723,6 +1888,8 @@ iblb_status iblb_destroy(iblb_ctx *c) {
     if (c->ib) (void)hipStreamDestroy(c->ib);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_chain) (void)hipEventDestroy(c->ev_chain);
+    if (c->ev_bulk) (void)hipEventDestroy(c->ev_bulk);
     if (c->host_obs) (void)hipHostFree(c->host_obs);
     if (c->host_status) (void)hipHostFree(c->host_status);
     delete c;

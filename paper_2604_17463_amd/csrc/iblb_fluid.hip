@@ -1,14 +1,18 @@
 // Fluid kernels of the IBLB wetting step (gfx950): the bulk fused
-// pull-stream / moments / BGK-Guo collision over every cell with the body
-// force only, the band kernel that gathers the spread interface force for
-// each stamped band tile and redoes the collision of its 64 cells with it,
-// and the per-box observables.
+// pull-stream / moments / BGK-Guo collision with the body force only, over
+// every cell outside this step's stamped band tiles; the band kernel, which
+// gathers the spread interface force for each stamped tile and does the
+// collision of its 64 cells with it; and the per-box observables.  The two
+// step kernels write disjoint cells and run side by side.
 #include "iblb_device.h"
 
 namespace iblb {
 
 // ------------------------------------------------------------------- bulk
-// Every cell of every box, F = body force.  A workgroup takes whole x-rows
+// Every cell of every box with F = body force, except (SKIP) the cells of
+// the band tiles this step's node pass stamped: the band kernel owns those
+// (it adds the spread force) and runs beside this kernel, so each cell is
+// pulled, collided and stored once per step.  A workgroup takes whole x-rows
 // (a row group); threads stride along x so the +-1 shifted loads of a row
 // stay inside one workgroup.  UROW: each wavefront lies in one row
 // (threads_x a multiple of 64), so the row addressing is wave-uniform and
@@ -16,9 +20,9 @@ namespace iblb {
 // streaming stores (they are read again only in the next step; pays off
 // once the two population buffers exceed the last-level cache).  EXT: some
 // box has a viscosity contrast or a moving wall (the plain variant carries
-// none of their registers).  Cells next to a mesh are recomputed by the band kernel
-// afterwards.
-template <int ST, bool UROW, bool NT, int CPT, bool EXT>
+// none of their registers).  Without SKIP the kernel is the plain
+// stream-collide of every cell (boxes without droplets, timing).
+template <int ST, bool UROW, bool NT, int CPT, bool EXT, bool SKIP>
 __global__ void __launch_bounds__(K1_MAX_THREADS)
     k_bulk(DevPtrs P, int parity, int full_u, float scale, float inv) {
     using S = Stor<ST>;
@@ -30,6 +34,9 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
     constexpr bool BUF = UROW && EB == 2;
     const int tx = threadIdx.x, ty = threadIdx.y, BX = blockDim.x, BY = blockDim.y;
     const IBLB_CONST RowGroup *rows = (const IBLB_CONST RowGroup *)P.rows;
+    // epoch of this step's stamps (written by the node pass, which this
+    // kernel follows); -2 never matches a stamp
+    const int epoch = SKIP ? ((const IBLB_GLOBAL int32_t *)P.step_epoch)[parity] : -2;
     for (int gi = blockIdx.x; gi < P.n_rowgroups; gi += gridDim.x) {
         const IBLB_CONST RowGroup &rg = rows[gi];
         const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + rg.box;
@@ -41,7 +48,10 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
         const R omega = (R)B->omega, guo = (R)B->guo, rho0 = (R)B->rho0;
         const R omega_in = (R)B->omega_in, guo_in = (R)B->guo_in;
         const bool contrast = B->contrast != 0, moving = B->moving != 0;
-        const IBLB_GLOBAL uint64_t *mprev = (const IBLB_GLOBAL uint64_t *)B->mask[parity ^ 1];
+        const IBLB_GLOBAL uint64_t *mask = (const IBLB_GLOBAL uint64_t *)B->mask[parity];
+        const IBLB_GLOBAL int32_t *stamp = (const IBLB_GLOBAL int32_t *)B->stamp[parity];
+        const int tnx = B->tnx, tny = B->tny;
+        const bool skip_box = SKIP && B->blk_end > B->blk_begin;  // only boxes holding droplets
         R kw[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) kw[a] = (R)(6.0 * B->rho0 * (double)scale * B->uw[a]);
@@ -75,9 +85,16 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
             for (int x = tx; x < nx; x += BX) {
                 R g[CPT][Q];
                 const XOff xo = x_off<EB>(x, nx);
+                bool mine[CPT];
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
-                    if (!on[k]) continue;
+                    mine[k] = on[k];
+                    if (skip_box && on[k])
+                        mine[k] = stamp[((int64_t)(rzk[k] >> TZS) * tny + (ryk[k] >> TYS)) * tnx + (x >> TXS)] != epoch;
+                }
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    if (!mine[k]) continue;
                     if constexpr (BUF)
                         pull_buf<ST>(rs, (uint32_t)pb, ra[k], xo, g[k]);
                     else
@@ -85,16 +102,15 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                 }
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
-                    if (!on[k]) continue;
+                    if (!mine[k]) continue;
                     R out[Q], u[3], rho;
                     const uint32_t own = ra[k].ro[1][1] + xo.c;
                     R om = omega, gu = guo;
                     if (EXT && moving && (ra[k].wlo || ra[k].whi)) wall_shift<R>(g[k], ra[k].wlo, ra[k].whi, kw);
                     if (EXT && contrast) {
-                        // inside bits of the previous step: a cell whose bit
-                        // changes since then lies in the band, which the band
-                        // kernel recomputes with this step's bits
-                        const uint64_t w = mprev[((int64_t)(rzk[k] >> 6) * ny + ryk[k]) * nx + x];
+                        // this step's inside bits (computed by the mesh
+                        // chain, which this kernel follows)
+                        const uint64_t w = mask[((int64_t)(rzk[k] >> 6) * ny + ryk[k]) * nx + x];
                         if ((w >> (rzk[k] & 63)) & 1ull) {
                             om = omega_in;
                             gu = guo_in;
@@ -288,8 +304,9 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
 // ------------------------------------------------------------------- band
 // One wavefront per stamped tile of this epoch, one lane per cell: gather
 // the spread force, then (COLLIDE) pull, collide with F = body force +
-// spread force, store the populations over the bulk result and write u to
-// the band; or (!COLLIDE, inspection) store F in the band.
+// spread force, store the populations (the bulk kernel leaves these cells
+// alone) and write u to the band; or (!COLLIDE, inspection) store F in the
+// band.
 // ONE_BOX: a single box, whose descriptor is read beside the list entry
 // rather than after it.
 template <int ST, bool COLLIDE, bool ONE_BOX>
@@ -486,22 +503,22 @@ __global__ void __launch_bounds__(256) k_box_obs_final(DevPtrs P, int box, int g
 }
 
 // ---------------------------------------------------------------- launchers
-template <int ST, bool UROW, bool NT>
+template <int ST, bool UROW, bool NT, bool SKIP>
 static void launch_bulk_c(const DevPtrs &P, int parity, int full_u, float scale, float inv, const Launch &L,
                           dim3 grid, dim3 block, hipStream_t s) {
     if (P.contrast || P.moving) {
         if (UROW && L.cpt == 2)
-            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
+            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, true, SKIP>), grid, block, 0, s, P, parity, full_u, scale, inv);
         else
-            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, true>), grid, block, 0, s, P, parity, full_u, scale, inv);
+            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, true, SKIP>), grid, block, 0, s, P, parity, full_u, scale, inv);
     } else if (UROW && L.cpt == 2) {
-        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, false, SKIP>), grid, block, 0, s, P, parity, full_u, scale, inv);
     } else {
-        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, false>), grid, block, 0, s, P, parity, full_u, scale, inv);
+        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, false, SKIP>), grid, block, 0, s, P, parity, full_u, scale, inv);
     }
 }
 
-template <int ST>
+template <int ST, bool SKIP>
 static hipError_t launch_bulk_t(const DevPtrs &P, int parity, int full_u, float scale, const Launch &L,
                                 hipStream_t s) {
     // never launch a shape the kernel was not compiled for
@@ -511,25 +528,32 @@ static hipError_t launch_bulk_t(const DevPtrs &P, int parity, int full_u, float 
     const float inv = 1.0f / scale;
     if (L.bx % 64 == 0) {
         if (L.nt)
-            launch_bulk_c<ST, true, true>(P, parity, full_u, scale, inv, L, grid, block, s);
+            launch_bulk_c<ST, true, true, SKIP>(P, parity, full_u, scale, inv, L, grid, block, s);
         else
-            launch_bulk_c<ST, true, false>(P, parity, full_u, scale, inv, L, grid, block, s);
+            launch_bulk_c<ST, true, false, SKIP>(P, parity, full_u, scale, inv, L, grid, block, s);
     } else {
         if (L.nt)
-            launch_bulk_c<ST, false, true>(P, parity, full_u, scale, inv, L, grid, block, s);
+            launch_bulk_c<ST, false, true, SKIP>(P, parity, full_u, scale, inv, L, grid, block, s);
         else
-            launch_bulk_c<ST, false, false>(P, parity, full_u, scale, inv, L, grid, block, s);
+            launch_bulk_c<ST, false, false, SKIP>(P, parity, full_u, scale, inv, L, grid, block, s);
     }
     return hipGetLastError();
 }
 
+template <int ST>
+static hipError_t launch_bulk_s(const DevPtrs &P, int parity, int full_u, float scale, const Launch &L,
+                                bool skip_band, hipStream_t s) {
+    return skip_band ? launch_bulk_t<ST, true>(P, parity, full_u, scale, L, s)
+                     : launch_bulk_t<ST, false>(P, parity, full_u, scale, L, s);
+}
+
 hipError_t launch_bulk(const DevPtrs &P, int storage, int parity, int full_u, float scale,
-                       const Launch &L, hipStream_t s) {
+                       const Launch &L, bool skip_band, hipStream_t s) {
     switch (storage) {
-    case 0: return launch_bulk_t<0>(P, parity, full_u, scale, L, s);
-    case 1: return launch_bulk_t<1>(P, parity, full_u, scale, L, s);
-    case 2: return launch_bulk_t<2>(P, parity, full_u, scale, L, s);
-    default: return launch_bulk_t<3>(P, parity, full_u, scale, L, s);
+    case 0: return launch_bulk_s<0>(P, parity, full_u, scale, L, skip_band, s);
+    case 1: return launch_bulk_s<1>(P, parity, full_u, scale, L, skip_band, s);
+    case 2: return launch_bulk_s<2>(P, parity, full_u, scale, L, skip_band, s);
+    default: return launch_bulk_s<3>(P, parity, full_u, scale, L, skip_band, s);
     }
 }
 

@@ -6,7 +6,9 @@
 //     f_i - w_i rho0 (scaled for FP16); a buffer holds the post-collision
 //     populations of the last step and the next step pulls from it;
 //   - band tiles of 16x4x1 cells (64 cells = one wavefront): an epoch
-//     stamp per tile and, in tile-major order [tile][3][64], the velocity u
+//     stamp per tile (two sets, by buffer parity, so that a step's node pass
+//     can run while the previous step's stream-collide still reads its set)
+//     and, in tile-major order [tile][3][64], the velocity u
 //     written by the band kernel in stamped tiles (and the spread force F
 //     for inspection);
 //   - with a viscosity contrast, two sets of inside bits [ceil(nz/64)][ny][nx]
@@ -51,7 +53,28 @@ constexpr int SCAN_GROUP = 256;    // boxes with at most this many node blocks: 
 // box whose blocks one scan pass of the gather covers needs no records).
 __host__ __device__ inline bool box_records(int blk_begin, int blk_end) {
     return blk_end - blk_begin > SCAN_GROUP;
-}             // ints per block region descriptor
+}
+
+// Tiles (of 1 << sh cells) that the cells lo .. lo + span - 1 of an axis of
+// n cells fall into, each once: `count` consecutive tiles from `first`,
+// counted modulo the axis's tile count ceil(n / 2^sh) on a periodic axis.
+// Periodic: lo in [0, n); a run that wraps past the last cell continues in
+// tile 0, and one that reaches back into its own first tile (or spans the
+// whole axis) covers every tile.  Otherwise the cells lie in [0, n).
+// span < 1 gives count 0.
+struct TileRun {
+    int first, count;
+};
+__host__ __device__ inline TileRun tile_run(int lo, int span, int n, int sh, bool per) {
+    if (span < 1) return {0, 0};
+    const int nt = (n + (1 << sh) - 1) >> sh;
+    const int t0 = lo >> sh, end = lo + span - 1;
+    if (!per || end < n) return {t0, (end >> sh) - t0 + 1};
+    if (span >= n) return {0, nt};
+    const int t1 = (end - n) >> sh;  // last tile after the wrap
+    if (t1 >= t0) return {0, nt};
+    return {t0, nt - t0 + t1 + 1};
+}
 
 // Velocity set in the library's order: 0 = rest, i and i+9 opposite (i=1..9).
 __host__ __device__ constexpr int cx_of(int i) {
@@ -79,7 +102,7 @@ __host__ __device__ constexpr double w_of(int i) {
 // base: their bytes may not exceed this.
 constexpr int64_t BUF_MAX_PLANE_GROUP = 0xFFFFFFFFll;
 
-enum : uint32_t { BIT_RHO = 1u, BIT_MACH = 2u, BIT_WALL = 4u, BIT_JUMP = 8u, BIT_BAND = 16u };
+enum : uint32_t { BIT_RHO = 1u, BIT_MACH = 2u, BIT_WALL = 4u, BIT_JUMP = 8u };
 
 struct BoxDev {
     int32_t nx, ny, nz, zbc;
@@ -91,7 +114,7 @@ struct BoxDev {
     void *f[2];                 // population buffers
     void *Fband, *uband;        // [n_tiles][3][64] of Real
     void *ufull;                // [3][plane] u of every cell (testing mode) or null
-    int32_t *stamp;             // [n_tiles]
+    int32_t *stamp[2];          // [n_tiles] epoch stamps, one set per buffer parity
     double tau, rho0, g[3];
     double omega, guo;          // 1/tau, 1 - 1/(2 tau)
     double cells_rho0;          // nx*ny*nz*rho0
@@ -146,6 +169,7 @@ struct DevPtrs {
     int32_t *tncand;            // [2][total_tiles] their number, by epoch parity
     int32_t *scan_all;          // [2][n_boxes] some block of the box could not record its tiles
     int32_t *ctr;               // step epoch
+    int32_t *step_epoch;        // [2] epoch of the last node pass, by buffer parity
     uint32_t *status;
     double *obs_part;           // observables scratch
     double *obs_out;            // per droplet [12], per box [2]
@@ -163,20 +187,22 @@ struct Launch {
     int nt;                     // bulk stream-collide writes with streaming stores
     int cpt;                    // rows per thread and row group pass (1 or 2; 2 needs bx % 64 == 0)
     int maxg;                   // cap on the grid (0: one workgroup per row group)
+    int after;                  // step schedule: 0 = the band kernel beside the bulk kernel, which
+                                // skips the band tiles; 1 = the bulk kernel over every cell beside
+                                // the mesh chain, then the band kernel over its band tiles
 };
 
 hipError_t launch_tri(const DevPtrs &P, bool f64, hipStream_t s);
 hipError_t launch_set_v0(const DevPtrs &P, bool f64, hipStream_t s);
-hipError_t launch_node(const DevPtrs &P, bool f64, int mode, hipStream_t s);
+hipError_t launch_node(const DevPtrs &P, bool f64, int mode, int parity, hipStream_t s);
 hipError_t launch_bulk(const DevPtrs &P, int storage, int parity, int full_u, float scale,
-                       const Launch &L, hipStream_t s);
+                       const Launch &L, bool skip_band, hipStream_t s);
 hipError_t launch_band(const DevPtrs &P, int storage, int parity, int full_u, float scale,
                        bool collide, hipStream_t s);
 hipError_t launch_interp(const DevPtrs &P, bool f64, int mode, double *Uout, hipStream_t s);
 hipError_t launch_epoch(const DevPtrs &P, hipStream_t s);
 hipError_t launch_inside(const DevPtrs &P, bool f64, int slot, hipStream_t s);
 hipError_t launch_mask_clear(const DevPtrs &P, int slot, hipStream_t s);
-hipError_t launch_mask_check(const DevPtrs &P, int slot, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_box_obs(const DevPtrs &P, int storage, int parity, float inv_scale,
                           hipStream_t s);

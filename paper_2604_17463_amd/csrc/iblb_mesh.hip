@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(64) k_set_v0(DevPtrs P) {
 // from LDS as broadcasts), then writes that partial region out for the tile
 // gather.
 template <typename R, int NR>
-__global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
+__global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode, int parity) {
     // NR waves spread NB / NR nodes each into their own LDS copy of the
     // region (NR = 1 keeps the LDS small when there are many more blocks
     // than compute units, NR > 1 shortens a block when there are few)
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
         const int nx = B.nx, ny = B.ny, nz = B.nz, tnx = B.tnx, tny = B.tny, tile_base = B.tile_base;
         const bool records = box_records(B.blk_begin, B.blk_end);
         const bool zper = B.zbc == 1;
-        IBLB_GLOBAL int32_t *const stamp = (IBLB_GLOBAL int32_t *)B.stamp;
+        IBLB_GLOBAL int32_t *const stamp = (IBLB_GLOBAL int32_t *)B.stamp[parity];
         const int node_off = D.node_off, n_nodes = D.n_nodes, n_exp = D.n_exp, m_exp = D.m_exp;
         const int chunk_off = D.chunk_off, n_chunks = D.n_chunks;
         const double kvol = D.kvol, V0 = D.V0, Aw = D.A, xi = D.xi;
@@ -142,6 +142,9 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
         const bool valid = (j - node_off) < n_nodes;
         const int dims[3] = {nx, ny, nz};
         const int ctr = mode == 0 ? *P.ctr : 0;
+        // the stream-collide of this step skips the tiles stamped with this
+        // epoch (the band kernel owns them); it finds the epoch here
+        if (mode == 0 && blk == 0 && lane == 0) P.step_epoch[parity] = ctr;
         double dV = 0.0;
         if (kvol > 0.0) {
             const double V = droplet_partial_sum(P.tri_part, chunk_off, n_chunks, lane);
@@ -304,8 +307,9 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
                          (int64_t)ex * ey * ez > MAXP;
         // every band tile that the stencil box covers records the block (slot
         // from an integer counter; the gather sorts the ids, so the order of
-        // the records does not matter); a block whose box spans more than 64
-        // cells on an axis, or a periodic axis whole, makes its box's gather scan
+        // the records does not matter, but each tile must list a block once);
+        // a box covering more than 64 tiles on an axis, or none (all stencil
+        // cells in a wall), makes its box's gather scan
         if (mode == 0 && records) {
             const int slot = ctr & 1;
             const int lo3[3] = {bl[0], bl[1], zl}, hi3[3] = {bh[0], bh[1], zh};
@@ -313,24 +317,20 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
             bool ok = true;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const int span = hi3[a] - lo3[a] + 1;
                 const bool per = a < 2 || zper;
-                if (span < 1 || span > 64 || (per && span > dims[a])) {
+                const int sh = a == 0 ? TXS : (a == 1 ? TYS : TZS);
+                const int nta = (dims[a] + (1 << sh) - 1) >> sh;
+                const TileRun run = tile_run(per ? wrapn(lo3[a], dims[a]) : lo3[a], hi3[a] - lo3[a] + 1,
+                                             dims[a], sh, per);
+                ntl[a] = run.count;
+                if (run.count < 1 || run.count > 64) {
                     ok = false;
-                    ntl[a] = 0;
                     continue;
                 }
-                int t = -1;
-                if (lane < span) {
-                    int cc = lo3[a] + lane;
-                    if (per) cc = wrapn(cc, dims[a]);
-                    t = cc >> (a == 0 ? TXS : (a == 1 ? TYS : TZS));
+                if (lane < run.count) {
+                    const int t = run.first + lane;
+                    tlist[a][lane] = t >= nta ? t - nta : t;
                 }
-                const int tprev = __shfl_up(t, 1, 64);
-                const bool first = lane < span && (lane == 0 || t != tprev);
-                const uint64_t m = __ballot(first);
-                ntl[a] = __popcll(m);
-                if (first) tlist[a][__popcll(m & ((1ull << lane) - 1ull))] = t;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -422,7 +422,7 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode) {
 // One wavefront per chunk of 64 tiles appends the chunk's stamped tiles to
 // the list of this epoch (one integer atomic per chunk; the order of the
 // list does not affect any result).  Also clears the other epoch's count.
-__global__ void __launch_bounds__(256) k_compact(DevPtrs P) {
+__global__ void __launch_bounds__(256) k_compact(DevPtrs P, int parity) {
     const int lane = threadIdx.x & 63;
     const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     const int ctr = *P.ctr;
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(256) k_compact(DevPtrs P) {
     const int box = P.tchunk_box[c];
     const BoxDev &B = P.boxes[box];
     const int lt = c * TILE_CELLS + lane - B.tile_base;
-    const bool st = lt < B.n_tiles && ((const IBLB_GLOBAL int32_t *)B.stamp)[lt] == ctr;
+    const bool st = lt < B.n_tiles && ((const IBLB_GLOBAL int32_t *)B.stamp[parity])[lt] == ctr;
     const uint64_t m = __ballot(st);
     if (m == 0) return;
     int base = 0;
@@ -753,21 +753,21 @@ hipError_t launch_set_v0(const DevPtrs &P, bool, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_node(const DevPtrs &P, bool f64, int mode, hipStream_t s) {
+hipError_t launch_node(const DevPtrs &P, bool f64, int mode, int parity, hipStream_t s) {
     if (P.nblk == 0) return hipSuccess;
     // few blocks: several waves per block share its spread; many blocks:
     // one wave per block, so that more blocks fit in a compute unit's LDS
     const bool many = P.nblk > P.n_cus;
     if (f64) {
-        if (many) hipLaunchKernelGGL((k_node<double, 1>), dim3(P.nblk), dim3(64), 0, s, P, mode);
-        else hipLaunchKernelGGL((k_node<double, 2>), dim3(P.nblk), dim3(128), 0, s, P, mode);
+        if (many) hipLaunchKernelGGL((k_node<double, 1>), dim3(P.nblk), dim3(64), 0, s, P, mode, parity);
+        else hipLaunchKernelGGL((k_node<double, 2>), dim3(P.nblk), dim3(128), 0, s, P, mode, parity);
     } else {
-        if (many) hipLaunchKernelGGL((k_node<float, 1>), dim3(P.nblk), dim3(64), 0, s, P, mode);
-        else hipLaunchKernelGGL((k_node<float, 4>), dim3(P.nblk), dim3(256), 0, s, P, mode);
+        if (many) hipLaunchKernelGGL((k_node<float, 1>), dim3(P.nblk), dim3(64), 0, s, P, mode, parity);
+        else hipLaunchKernelGGL((k_node<float, 4>), dim3(P.nblk), dim3(256), 0, s, P, mode, parity);
     }
     if (mode == 0 && P.total_tiles > 0) {
         const int chunks = P.total_tiles / TILE_CELLS;
-        hipLaunchKernelGGL(k_compact, dim3((chunks + 3) / 4), dim3(256), 0, s, P);
+        hipLaunchKernelGGL(k_compact, dim3((chunks + 3) / 4), dim3(256), 0, s, P, parity);
     }
     return hipGetLastError();
 }
@@ -893,35 +893,6 @@ __global__ void __launch_bounds__(256) k_mask_clear(DevPtrs P, int slot) {
         m[i] = 0;
 }
 
-// The bulk kernel relaxes with the previous step's inside bits and the band
-// kernel redoes the stamped tiles with this step's.  That equals using this
-// step's bits everywhere only while every cell whose bit changed lies in a
-// stamped tile; a changed cell outside them (triangles larger than the node
-// stencils) sets BIT_BAND.  Runs after this step's stamps are written.
-__global__ void __launch_bounds__(256) k_mask_check(DevPtrs P, int slot) {
-    const BoxDev &B = P.boxes[blockIdx.y];
-    if (!B.contrast) return;
-    const int nx = B.nx, ny = B.ny, nz = B.nz;
-    const int64_t n = (int64_t)B.nzw * ny * nx;
-    const uint64_t *m0 = B.mask[slot], *m1 = B.mask[slot ^ 1];
-    const int ctr = *P.ctr;
-    bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t d = m0[i] ^ m1[i];
-        if (!d) continue;
-        const int x = (int)(i % nx);
-        const int64_t r = i / nx;
-        const int y = (int)(r % ny), zw = (int)(r / ny);
-        while (d) {
-            const int z = zw * 64 + __builtin_ctzll(d);
-            d &= d - 1;
-            if (z >= nz) break;
-            if (B.stamp[band_tile(x, y, z, B.tnx, B.tny)] != ctr) bad = true;
-        }
-    }
-    if (bad) atomicOr(P.status, BIT_BAND);
-}
-
 namespace {
 dim3 mask_grid(const DevPtrs &P) {
     const int64_t g = ((int64_t)P.mask_words + 255) / 256;
@@ -932,12 +903,6 @@ dim3 mask_grid(const DevPtrs &P) {
 hipError_t launch_mask_clear(const DevPtrs &P, int slot, hipStream_t s) {
     if (!P.contrast) return hipSuccess;
     hipLaunchKernelGGL(k_mask_clear, mask_grid(P), dim3(256), 0, s, P, slot);
-    return hipGetLastError();
-}
-
-hipError_t launch_mask_check(const DevPtrs &P, int slot, hipStream_t s) {
-    if (!P.contrast) return hipSuccess;
-    hipLaunchKernelGGL(k_mask_check, mask_grid(P), dim3(256), 0, s, P, slot);
     return hipGetLastError();
 }
 

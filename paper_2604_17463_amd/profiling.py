@@ -4,9 +4,16 @@
     rocprofv3 --pmc WRITE_SIZE -d OUT -- python -m paper_2604_17463_amd.profiling
     rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2604_17463_amd.profiling
 
-With --steps WORKLOAD N it instead runs N graph-replayed, autotuned FP32
-steps of a named workload (spreading, batched or multidroplet) after 20
-warm-up steps and prints the step time, for kernel traces of whole steps.
+With --steps WORKLOAD N it instead runs N graph-replayed FP32 steps of a
+named workload (spreading, batched or multidroplet) after 20 warm-up steps
+and prints the step time, for kernel traces of whole steps.  With --launch
+the bulk launch is set as given and nothing is autotuned, so that a trace
+holds only the steps' own launches; without it the context autotunes at
+init (its candidate launches then appear in a trace too).
+
+With --copy GIB it instead copies a device buffer of that size (torch's copy
+kernel) 3 + `reps` times, the plain-copy ceiling of the memory system at
+that footprint.
 
 First a plain device copy of a known size (torch's copy kernel) serves as
 the calibration of the memory counters, then the bulk kernel runs 3 + `reps`
@@ -31,10 +38,16 @@ def main():
                     help="the same on the 256x256x128 box")
     ap.add_argument("--steps", nargs=2, metavar=("WORKLOAD", "N"),
                     help="run N steps of spreading, batched or multidroplet instead")
+    ap.add_argument("--launch", type=int, nargs=5, default=None,
+                    help="with --steps: bulk launch to set (no autotuning)")
+    ap.add_argument("--copy", type=float, default=0.0, metavar="GIB",
+                    help="time a device copy of this many GiB instead")
     args = ap.parse_args()
     import torch
     if args.steps:
-        return run_steps(args.steps[0], int(args.steps[1]))
+        return run_steps(args.steps[0], int(args.steps[1]), args.launch)
+    if args.copy > 0:
+        return run_copy(args.copy, args.reps)
 
     import paper_2604_17463_amd as P
     from iblb_inputs import configs
@@ -60,7 +73,28 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def run_steps(name, n):
+def run_copy(gib, reps):
+    """Device-to-device copy of `gib` GiB (torch's copy kernel): mean time
+    and rate over `reps` copies after 3 untimed ones."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_each_way": n * 4, "ms": ms,
+                      "GBs_read_plus_write": 2 * n * 4 / (ms * 1e-3) / 1e9}), flush=True)
+
+
+def run_steps(name, n, launch=None):
     import time
 
     import torch
@@ -69,7 +103,10 @@ def run_steps(name, n):
     from iblb_inputs import configs
     wl = {"spreading": configs.spreading_c2, "batched": configs.batched_c4,
           "multidroplet": configs.multidroplet_c5}[name]()
-    sim = P.Simulation(wl, storage=P.IBLB_F32, flags=P.IBLB_FLAG_GRAPH | P.IBLB_FLAG_AUTOTUNE)
+    flags = P.IBLB_FLAG_GRAPH | (0 if launch else P.IBLB_FLAG_AUTOTUNE)
+    sim = P.Simulation(wl, storage=P.IBLB_F32, flags=flags)
+    if launch:
+        sim.set_launch(*launch)
     sim.step(20)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -97,3 +97,46 @@ def test_paper_scale_sphere_touches_the_wall_through_a_neck():
     assert radii[0] < 0.7 * max(radii)                       # a neck at the wall
     assert abs(d["volume"] / v0 - 1.0) < 2e-3
     s.close()
+
+
+def test_paper_scale_forces_spread_and_step_match_oracle():
+    # oracle parity at the scale of the paper's runs: after 300 GPU steps of
+    # the 250 x 250 x 150 / 118,580-triangle run (tau = 0.732), on the GPU's
+    # own node positions, the nodal forces (2e-5 of the largest), the spread
+    # force field over all 9.4 M cells (relative L2 1e-6) and the stamped
+    # tiles (bit-exact); then the GPU's next step against the oracle's step
+    # from the GPU's state (deviations 1e-5, nodes 1e-6 lu, mass 1e-9)
+    import numpy as np
+
+    import oracle
+    import paper_2604_17463_amd as P
+    from _helpers import deviation, lib_to_oracle_perm, rel_l2, to_oracle
+    say("paper-scale forces, spread and one step against the oracle")
+    wl = configs.paper_spreading(0.732)
+    box, dr = wl.boxes[0], wl.droplets[0]
+    shape = (box.nz, box.ny, box.nx)
+    s = P.Simulation(wl, storage=1, flags=1)
+    s.step(300)
+    q = s.read_nodes(0)
+    A = oracle.wetting_A(dr.sigma, dr.theta_eq, dr.xi, dr.n_exp, dr.m_exp)
+    want = oracle.node_forces(dr.tris, q, dr.sigma, A, dr.xi, dr.n_exp, dr.m_exp, dr.k_vol,
+                              oracle.volume(dr.tris, dr.nodes))["phi"]
+    got = s.compute_forces(0)
+    assert np.abs(got - want).max() < 2e-5 * np.abs(want).max()
+    F, flags = s.compute_spread(0)
+    Fo, _ = oracle.spread(shape, box.zbc, q, got)
+    assert rel_l2(F, Fo) < 1e-6
+    assert np.array_equal(flags, oracle.touched_tiles(q, shape, box.zbc, tile=P.band_tile()))
+    del F, Fo
+    perm = lib_to_oracle_perm()
+    f0 = to_oracle(s.read_state(0), perm)
+    ref = oracle.OracleSim(wl, f0=[f0])
+    ref.q[0] = q.copy()
+    ref.step(1)
+    s.step(1)
+    f1 = to_oracle(s.read_state(0), perm)
+    assert rel_l2(deviation(f1), deviation(ref.f[0])) < 1e-5
+    assert np.abs(s.read_nodes(0) - ref.q[0]).max() < 1e-6
+    _, boxes = s.observables()
+    assert boxes[0]["status_bits"] == 0
+    assert abs(boxes[0]["mass"] - oracle.mass(ref.f[0])) < 1e-9 * oracle.mass(ref.f[0])

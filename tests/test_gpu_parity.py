@@ -283,7 +283,7 @@ def test_bulk_launch_configurations_give_identical_results(storage):
     wl = configs.plain_c1()
     ref = None
     for launch in ((32, 2, 1, 0, 0), (64, 1, 2, 0, 0), (64, 4, 2, 1, 0), (64, 2, 1, 1, 5),
-                   (64, 1, 2, 0, 3), (256, 1, 2, 1, 1)):
+                   (64, 1, 2, 0, 3), (256, 1, 2, 1, 1), (32, 2, 1, 0, 0, 1), (64, 1, 2, 1, 7, 1)):
         s = sim(wl, storage, flags=GRAPH)
         s.set_launch(*launch)
         s.step(30)
@@ -359,14 +359,15 @@ def test_set_launch_rejects_shapes_beyond_the_kernel_bound():
         with pytest.raises(P.IblbError) as e:
             s.set_launch(bx, by)
         assert e.value.code == -1
-    for bad in ((64, 4, 3, 0, 0), (32, 2, 2, 0, 0), (64, 4, 1, 2, 0), (64, 4, 1, 0, -1)):
+    for bad in ((64, 4, 3, 0, 0), (32, 2, 2, 0, 0), (64, 4, 1, 2, 0), (64, 4, 1, 0, -1),
+                (64, 4, 1, 0, 0, 2)):
         with pytest.raises(P.IblbError) as e:
             s.set_launch(*bad)
         assert e.value.code == -1
     s.set_launch(64, 4)
-    assert s.get_launch() == (64, 4, 1, 0, 0)
-    s.set_launch(64, 4, 2, 1, 7)
-    assert s.get_launch() == (64, 4, 2, 1, 7)
+    assert s.get_launch() == (64, 4, 1, 0, 0, 0)
+    s.set_launch(64, 4, 2, 1, 7, 1)
+    assert s.get_launch() == (64, 4, 2, 1, 7, 1)
     s.step(3)
 
 
