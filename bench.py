@@ -520,7 +520,7 @@ def main():
     tr = traffic_record()
     traffic = None
     if (tr and tr.get("workload") == wl.name and tr.get("storage") == args.storage
-            and tuple(tr.get("launch", ()))[:4] == tuple(launch)[:4]):
+            and tuple(tr.get("launch", ()))[:5] == tuple(launch)[:5]):
         traffic = tr["hbm_bytes_per_launch"]
     step_bytes = bytes_k1 + band * BYTES_PER_BAND_CELL + nodes * BYTES_PER_NODE
     out = {

@@ -209,6 +209,26 @@ iblb_status iblb_init(const iblb_config *cfg, void *dev_workspace, size_t bytes,
  * reported by iblb_observables, IBLB_E_DEVICE when a launch fails. */
 iblb_status iblb_step(struct iblb_ctx *ctx, int64_t n_steps);
 
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same n_steps time steps as iblb_step, bit for bit, with the step's own
+ * scratch arrays (triangle records and FP64 partial sums, node-block
+ * boxes, region descriptors and partial spread regions, the stamped-tile
+ * list and the per-tile block records) taken from a fixed device array of
+ * the library, 32 MiB per GPU, held from the library's load until the
+ * process ends, instead of from the context's workspace.  Allocates
+ * nothing and replays no graph: the kernels of each step are enqueued on
+ * the context's stream one after another, with the step's advection
+ * applied at its end.  The step scratch of a configuration grows with its
+ * nodes (about 560 B per node in FP32, 1.1 KB in FP64) and its box cells
+ * (1.25 B per cell): the 128x128x64 spreading workload needs about 7 MB.
+ * One that exceeds 32 MiB returns IBLB_E_WORKSPACE with the bytes it
+ * needs.  The array is shared by every
+ * context on the GPU and keeps the last call's contents (the records that
+ * must start empty are cleared by each call): calls that overlap on one
+ * GPU, from any context or thread, race.  Asynchronous like iblb_step. */
+iblb_status iblb_step_static(struct iblb_ctx *ctx, int64_t n_steps);
+
 /* Observables of the current state (per droplet and per box).  Either
  * output may be NULL.  Synchronising.  Returns IBLB_E_UNSTABLE (after
  * filling the outputs) when any status bit is set; that state is sticky. */

@@ -20,7 +20,8 @@ IBLB_FLAG_GRAPH, IBLB_FLAG_AUTOTUNE, IBLB_FLAG_FULL_U = 1, 2, 4
 IBLB_BIT_RHO, IBLB_BIT_MACH, IBLB_BIT_WALL, IBLB_BIT_JUMP, IBLB_BIT_BAND = 1, 2, 4, 8, 16
 
 EXPORTS = (
-    "iblb_velocity_set", "iblb_workspace_size", "iblb_init", "iblb_step", "iblb_observables",
+    "iblb_velocity_set", "iblb_workspace_size", "iblb_init", "iblb_step", "iblb_step_static",
+    "iblb_observables",
     "iblb_read_state", "iblb_read_window", "iblb_write_state", "iblb_read_nodes", "iblb_write_nodes",
     "iblb_compute_forces", "iblb_compute_spread", "iblb_interpolate", "iblb_read_bins",
     "iblb_read_csr", "iblb_read_inside", "iblb_state_size", "iblb_save_state", "iblb_load_state",
@@ -84,6 +85,7 @@ def load():
     L.iblb_workspace_size.argtypes = [C.POINTER(iblb_config), C.POINTER(C.c_size_t)]
     L.iblb_init.argtypes = [C.POINTER(iblb_config), vp, C.c_size_t, vp, C.POINTER(vp)]
     L.iblb_step.argtypes = [vp, i64]
+    L.iblb_step_static.argtypes = [vp, i64]
     L.iblb_observables.argtypes = [vp, C.POINTER(iblb_obs), i32, C.POINTER(iblb_box_obs), i32]
     L.iblb_read_state.argtypes = [vp, i32, dp, dp]
     L.iblb_read_window.argtypes = [vp, i32, ip, ip, dp, dp]
@@ -215,6 +217,11 @@ class Simulation:
 
     def step(self, n=1):
         self._chk(load().iblb_step(self.ctx, int(n)))
+
+    def step_static(self, n=1):
+        """The same steps, with the step scratch in the library's fixed
+        device array (no allocation)."""
+        self._chk(load().iblb_step_static(self.ctx, int(n)))
 
     def observables(self, raise_unstable=True):
         drops = (iblb_obs * max(self.nd, 1))()

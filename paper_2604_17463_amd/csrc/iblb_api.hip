@@ -20,7 +20,35 @@
 
 using namespace iblb;
 
+// Fixed device scratch of iblb_step_static: the per-step arrays of the
+// spreading (triangle records and FP64 partial sums, node-block bounding
+// boxes, region descriptors and partial regions, stamped-tile list and its
+// lengths, per-tile block records) for callers that cannot allocate.  Each
+// device holds its own copy from the library's load until the process ends.
+// Host code never uses this name as an address: each device's address comes
+// from hipGetSymbolAddress, taken once per device at iblb_init.
+constexpr size_t SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device dev (current), looked up once.
+hipError_t scratch_address(int dev, char **out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 thread_local std::string g_last_error = "no error";
 
@@ -69,6 +97,9 @@ struct Plan {
            off_tchunk = 0, off_tcand = 0, off_tncand = 0, off_scan = 0, off_ctr = 0, off_step_epoch = 0, off_status = 0, off_obs_part = 0,
            off_obs_out = 0,
            off_uout = 0, total = 0;
+    // the same per-step arrays inside the fixed scratch (iblb_step_static)
+    size_t st_trec = 0, st_tri_part = 0, st_bbox = 0, st_breg = 0, st_part = 0, st_tile_list = 0,
+           st_tile_count = 0, st_tcand = 0, st_tncand = 0, st_scan = 0, st_total = 0;
 };
 
 bool finite(double v) { return std::isfinite(v); }
@@ -345,6 +376,18 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
     p.off_obs_out = take(((size_t)p.drops.size() * OBS_DROP + p.boxes.size() * OBS_BOX) * 8);
     p.off_uout = take(3 * N * 8);
     p.total = round_up(o, ALIGN);
+    o = 0;
+    p.st_trec = take((size_t)TREC * p.Ttot * p.real);
+    p.st_tri_part = take(2 * (size_t)p.n_chunks * 8);
+    p.st_bbox = take(6 * (size_t)p.nblk * 4);
+    p.st_breg = take((size_t)BREG * p.nblk * 4);
+    p.st_part = take((size_t)3 * MAXP * p.nblk * p.real);
+    p.st_tile_list = take((size_t)p.total_tiles * 8);
+    p.st_tile_count = take(2 * 4);
+    p.st_tcand = take((size_t)p.total_tiles * MAXC * 4);
+    p.st_tncand = take((size_t)2 * p.total_tiles * 4);
+    p.st_scan = take((size_t)2 * p.boxes.size() * 4);
+    p.st_total = round_up(o, ALIGN);
     return IBLB_OK;
 }
 
@@ -357,6 +400,7 @@ struct iblb_ctx {
     hipStream_t capture = nullptr;  // origin stream of graph captures
     hipStream_t ib = nullptr;       // second stream: the mesh chain of a step
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    char *scratch = nullptr;  // this device's fixed scratch (iblb_step_static)
     DevPtrs P{};
     Launch L{};
     hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][advect first]
@@ -915,6 +959,7 @@ static iblb_status init_device(iblb_ctx *c) {
         HIPCHK(c, hipGetDevice(&dev));
         HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         P.n_cus = std::max(cus, 1);
+        HIPCHK(c, scratch_address(dev, &c->scratch));
     }
 
     // host tables
@@ -1188,6 +1233,76 @@ iblb_status iblb_step(iblb_ctx *c, int64_t n) {
         }
         k += m;
     }
+    return IBLB_OK;
+}
+
+iblb_status iblb_step_static(iblb_ctx *c, int64_t n) {
+    if (!c) return set_err(nullptr, IBLB_E_INVAL, "ctx is NULL");
+    if (n < 0) return set_err(c, IBLB_E_INVAL, "n_steps < 0");
+    if (c->unstable) return set_err(c, IBLB_E_STATE, "context is unstable; no further steps");
+    const Plan &p = c->plan;
+    if (p.st_total > SCRATCH_BYTES)
+        return set_err(c, IBLB_E_WORKSPACE,
+                       "iblb_step_static: the configuration needs " + std::to_string(p.st_total) +
+                           " bytes of step scratch, the fixed scratch holds " + std::to_string(SCRATCH_BYTES));
+    if (n == 0) return IBLB_OK;
+    {
+        iblb_status st = flush(c);  // a pending advection of an iblb_step run
+        if (st != IBLB_OK) return st;
+    }
+    hipStream_t s = c->stream;
+    const bool f64 = is_f64(c);
+    const int full_u = (p.flags & IBLB_FLAG_FULL_U) ? 1 : 0;
+    const float scale = (float)p.scale;
+    if (p.nblk == 0) {
+        for (int64_t k = 0; k < n; ++k) {
+            HIPCHK(c, launch_bulk(c->P, p.storage, c->parity, full_u, scale, c->L, false, s));
+            c->parity ^= 1;
+            ++c->step;
+        }
+        c->u_valid = true;
+        return IBLB_OK;
+    }
+    // the step's arrays inside the fixed scratch; the records that must
+    // start empty are cleared by a fill kernel (the scratch keeps whatever
+    // the last call on this device left)
+    DevPtrs V = c->P;
+    char *const S = c->scratch;
+    V.trec = S + p.st_trec;
+    V.tri_part = (double *)(S + p.st_tri_part);
+    V.bbox = (int32_t *)(S + p.st_bbox);
+    V.breg = (int32_t *)(S + p.st_breg);
+    V.part = S + p.st_part;
+    V.tile_list = (int32_t *)(S + p.st_tile_list);
+    V.tile_count = (int32_t *)(S + p.st_tile_count);
+    V.tcand = (int32_t *)(S + p.st_tcand);
+    V.tncand = (int32_t *)(S + p.st_tncand);
+    V.scan_all = (int32_t *)(S + p.st_scan);
+    HIPCHK(c, launch_fill_i32(V.tncand, 0, 2 * (int64_t)p.total_tiles, s));
+    HIPCHK(c, launch_fill_i32(V.tile_count, 0, 2, s));
+    HIPCHK(c, launch_fill_i32(V.scan_all, 0, 2 * (int64_t)p.boxes.size(), s));
+    // one queue, in order: mesh chain, band tiles, every other cell, then the
+    // advection (none is left pending)
+    for (int64_t k = 0; k < n; ++k) {
+        const int par = c->parity;
+        const iblb_status st = compute_masks(c, par, s);  // inside bits: workspace arrays only
+        if (st != IBLB_OK) return st;
+        HIPCHK(c, launch_tri(V, f64, s));
+        HIPCHK(c, launch_node(V, f64, 0, par, s));
+        HIPCHK(c, launch_band(V, p.storage, par, full_u, scale, true, s));
+        HIPCHK(c, launch_bulk(V, p.storage, par, full_u, scale, c->L, true, s));
+        HIPCHK(c, launch_interp(V, f64, 0, nullptr, s));
+        c->last_step_epoch = c->epoch;
+        c->last_step_parity = par;
+        ++c->epoch;  // the advection starts the next epoch
+        c->parity ^= 1;
+        ++c->step;
+    }
+    c->u_valid = true;
+    // the workspace's records start empty for a later iblb_step
+    HIPCHK(c, launch_fill_i32(c->P.tncand, 0, 2 * (int64_t)p.total_tiles, s));
+    HIPCHK(c, launch_fill_i32(c->P.tile_count, 0, 2, s));
+    HIPCHK(c, launch_fill_i32(c->P.scan_all, 0, 2 * (int64_t)p.boxes.size(), s));
     return IBLB_OK;
 }
 

@@ -1,24 +1,28 @@
-"""Driver for rocprofv3 runs of the bulk stream-collide kernel.
+"""Driver for rocprofv3 runs of the IBLB kernels.
 
-    rocprofv3 --pmc FETCH_SIZE -d OUT -- python -m paper_2604_17463_amd.profiling
-    rocprofv3 --pmc WRITE_SIZE -d OUT -- python -m paper_2604_17463_amd.profiling
-    rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2604_17463_amd.profiling
+    rocprofv3 --pmc FETCH_SIZE -d OUT -- python -m paper_2604_17463_amd.profiling [--bulk ...]
+    rocprofv3 --pmc WRITE_SIZE -d OUT -- python -m paper_2604_17463_amd.profiling [--bulk ...]
+    rocprofv3 --kernel-trace --stats -d OUT -- python -m paper_2604_17463_amd.profiling [--bulk ...]
+
+By default (or with --bulk NAME=LAUNCH ...) a plain device copy of a known
+size (torch's copy kernel) first serves as the calibration of the memory
+counters; then the bulk stream-collide kernel runs over every cell, 3 +
+`reps` times, on each named workload (spreading, box256, multidroplet,
+batched) in the given launch shape (threads_x, rows, cells_per_thread,
+streaming_stores, max_workgroups).
 
 With --steps WORKLOAD N it instead runs N graph-replayed FP32 steps of a
-named workload (spreading, batched or multidroplet) after 20 warm-up steps
-and prints the step time, for kernel traces of whole steps.  With --launch
-the bulk launch is set as given and nothing is autotuned, so that a trace
-holds only the steps' own launches; without it the context autotunes at
-init (its candidate launches then appear in a trace too).
+named workload after 20 warm-up steps and prints the step time and the
+band cells of the last step, for kernel traces and counters of whole steps.
+With --launch the bulk launch and step schedule are set as given and
+nothing is autotuned, so that a trace holds only the steps' own launches;
+without it the context autotunes at init (its candidate launches then
+appear in a trace too).  --eager launches the kernels one by one instead of
+replaying graphs.
 
 With --copy GIB it instead copies a device buffer of that size (torch's copy
 kernel) 3 + `reps` times, the plain-copy ceiling of the memory system at
 that footprint.
-
-First a plain device copy of a known size (torch's copy kernel) serves as
-the calibration of the memory counters, then the bulk kernel runs 3 + `reps`
-times in a fixed launch shape on the 128x128x64 spreading workload and on a
-256x256x128 box.
 """
 from __future__ import annotations
 
@@ -26,32 +30,42 @@ import argparse
 import json
 
 
+WORKLOADS = ("spreading", "box256", "multidroplet", "batched")
+
+
+def _workload(name):
+    from iblb_inputs import configs
+    from iblb_inputs.configs import Box, Workload
+    if name == "box256":
+        return Workload("box-256x256x128", [Box(256, 256, 128, tau=0.6)], [])
+    return {"spreading": configs.spreading_c2, "batched": configs.batched_c4,
+            "multidroplet": configs.multidroplet_c5}[name]()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--storage", type=int, default=1)
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--launch-spreading", type=int, nargs=5, default=(128, 1, 1, 0, 1024),
-                    help="threads_x rows cells_per_thread streaming_stores max_workgroups of the "
-                         "bulk launch on the spreading workload")
-    ap.add_argument("--launch-box", type=int, nargs=5, default=(256, 1, 1, 1, 0),
-                    help="the same on the 256x256x128 box")
+    ap.add_argument("--bulk", nargs="+", default=["spreading=128,1,1,0,1024", "box256=256,1,1,1,0"],
+                    metavar="NAME=LAUNCH",
+                    help="workloads and bulk launches (threads_x,rows,cells_per_thread,"
+                         "streaming_stores,max_workgroups) for the counter runs")
     ap.add_argument("--steps", nargs=2, metavar=("WORKLOAD", "N"),
                     help="run N steps of spreading, batched or multidroplet instead")
-    ap.add_argument("--launch", type=int, nargs=5, default=None,
-                    help="with --steps: bulk launch to set (no autotuning)")
+    ap.add_argument("--launch", type=int, nargs=6, default=None,
+                    help="with --steps: bulk launch and schedule to set (no autotuning)")
+    ap.add_argument("--eager", action="store_true", help="with --steps: no graph replay")
     ap.add_argument("--copy", type=float, default=0.0, metavar="GIB",
                     help="time a device copy of this many GiB instead")
     args = ap.parse_args()
     import torch
     if args.steps:
-        return run_steps(args.steps[0], int(args.steps[1]), args.launch)
+        return run_steps(args.steps[0], int(args.steps[1]), args.launch, args.eager)
     if args.copy > 0:
         return run_copy(args.copy, args.reps)
 
     import paper_2604_17463_amd as P
-    from iblb_inputs import configs
-    from iblb_inputs.configs import Box, Workload
 
     n = args.copy_mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -59,10 +73,13 @@ def main():
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
+    del a, b
     res = {"copy_bytes_each_way": n * 4}
-    for name, wl, launch in (("spreading", configs.spreading_c2(), args.launch_spreading),
-                             ("box256", Workload("box-256x256x128", [Box(256, 256, 128, tau=0.6)], []),
-                              args.launch_box)):
+    for item in args.bulk:
+        name, launch = item.split("=")
+        launch = [int(v) for v in launch.split(",")]
+        assert name in WORKLOADS, name
+        wl = _workload(name)
         sim = P.Simulation(wl, storage=args.storage, dev_scale=4096.0 if args.storage == 2 else 1.0)
         sim.set_launch(*launch)
         sim.time_stream_collide(reps=3)
@@ -70,6 +87,7 @@ def main():
         res[name] = {"workload": wl.name, "cells": wl.cells, "bulk_ms": ms,
                      "launch": list(sim.get_launch())}
         sim.close()
+        print(json.dumps({name: res[name]}), flush=True)
     print(json.dumps(res), flush=True)
 
 
@@ -94,16 +112,14 @@ def run_copy(gib, reps):
                       "GBs_read_plus_write": 2 * n * 4 / (ms * 1e-3) / 1e9}), flush=True)
 
 
-def run_steps(name, n, launch=None):
+def run_steps(name, n, launch=None, eager=False):
     import time
 
     import torch
 
     import paper_2604_17463_amd as P
-    from iblb_inputs import configs
-    wl = {"spreading": configs.spreading_c2, "batched": configs.batched_c4,
-          "multidroplet": configs.multidroplet_c5}[name]()
-    flags = P.IBLB_FLAG_GRAPH | (0 if launch else P.IBLB_FLAG_AUTOTUNE)
+    wl = _workload(name)
+    flags = (0 if eager else P.IBLB_FLAG_GRAPH) | (0 if launch else P.IBLB_FLAG_AUTOTUNE)
     sim = P.Simulation(wl, storage=P.IBLB_F32, flags=flags)
     if launch:
         sim.set_launch(*launch)
@@ -113,8 +129,13 @@ def run_steps(name, n, launch=None):
     sim.step(n)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    band = 0
+    for b in range(len(wl.boxes)):
+        _, flags_b = sim.compute_spread(b, want_F=False)
+        band += int(flags_b.sum()) * 64
     print(json.dumps({"workload": wl.name, "cells": wl.cells, "steps": n, "ms_per_step": dt / n * 1e3,
-                      "launch": list(sim.get_launch())}), flush=True)
+                      "launch": list(sim.get_launch()), "graph": not eager,
+                      "band_cells_at_end": band}), flush=True)
     sim.close()
 
 
