@@ -5,7 +5,7 @@
 //     (sx = x pitch rounded up to a 128-byte row), storing deviations
 //     f_i - w_i rho0 (scaled for FP16); a buffer holds the post-collision
 //     populations of the last step and the next step pulls from it;
-//   - band tiles of 16x4x1 cells (64 cells = one wavefront): an epoch
+//   - band tiles of 32x2x1 cells (64 cells = one wavefront): an epoch
 //     stamp per tile (two sets, by buffer parity, so that a step's node pass
 //     can run while the previous step's stream-collide still reads its set)
 //     and, in tile-major order [tile][3][64], the velocity u
@@ -23,11 +23,13 @@
 namespace iblb {
 
 constexpr int Q = 19;
-// Band tile: 16 consecutive cells along x, 4 along y, 1 along z (64 cells,
-// one wavefront).  Population rows are contiguous along x, so a tile reads
-// and writes 64-byte runs of each FP32 population row.
-constexpr int TX = 16, TY = 4, TZ = 1;
-constexpr int TXS = 4, TYS = 2, TZS = 0;  // log2 of the tile extents
+// Band tile: 32 consecutive cells along x, 2 along y, 1 along z (64 cells,
+// one wavefront).  Population rows are contiguous along x and padded to
+// 128-byte lines, so a tile reads and writes whole 128-byte lines of each
+// FP32 population row, and the bulk kernel, which skips the band tiles,
+// skips whole lines.
+constexpr int TX = 32, TY = 2, TZ = 1;
+constexpr int TXS = 5, TYS = 1, TZS = 0;  // log2 of the tile extents
 constexpr int TILE_CELLS = TX * TY * TZ;
 static_assert(TILE_CELLS == 64 && (1 << TXS) == TX && (1 << TYS) == TY && (1 << TZS) == TZ, "band tile");
 

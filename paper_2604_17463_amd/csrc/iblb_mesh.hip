@@ -245,43 +245,36 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode, int parit
             }
             if (mode == 0) {
                 // epoch stamp of every tile holding a stencil cell (same value
-                // from every writer, so plain stores).  Along x and y the four
-                // stencil cells start at s0 (wrapped) and may wrap once: their
-                // tiles are those of s0, of the last cell before the wrap and
-                // of the last cell after it (tiles at least four wide there,
-                // so the part after the wrap lies in tile 0).  Along z each
-                // cell is its own tile (one deep) unless it lies in a wall.
-                static_assert(TX >= 4 && TY >= 4 && TZ == 1, "stamp pattern of the band tile shape");
-                int xt[3], yt[3];
-                bool xu[3], yu[3];
-                auto axis = [](int c0, int n, int sh, int (&t)[3], bool (&u)[3]) {
-                    const bool wraps = c0 + 3 >= n;
-                    t[0] = c0 >> sh;
-                    t[1] = (wraps ? n - 1 : c0 + 3) >> sh;
-                    t[2] = wraps ? (c0 + 3 - n) >> sh : t[1];
-                    u[0] = true;
-                    u[1] = t[1] != t[0];
-                    u[2] = t[2] != t[0] && t[2] != t[1];
-                };
-                axis(s0[0], nx, TXS, xt, xu);
-                axis(s0[1], ny, TYS, yt, yu);
-                int zt[4];
-                bool zv[4];
+                // from every writer, so plain stores).  Per axis the four
+                // stencil cells from s0 (wrapped on a periodic axis; cells in
+                // a wall are left out) and the tile of each, kept where it
+                // differs from the tiles of the cells before it
+                int t3[3][4];
+                bool u3[3][4];
 #pragma unroll
-                for (int o = 0; o < 4; ++o) {
-                    int c = s0[2] + o;
-                    if (zper && c >= nz) c -= nz;
-                    zv[o] = c >= 0 && c < nz;
-                    zt[o] = c;
+                for (int a = 0; a < 3; ++a) {
+                    const int sh = a == 0 ? TXS : (a == 1 ? TYS : TZS);
+                    const bool per = a < 2 || zper;
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) {
+                        int c = s0[a] + o;
+                        if (per && c >= dims[a]) c -= dims[a];
+                        const bool v = c >= 0 && c < dims[a];
+                        t3[a][o] = c >> sh;
+                        bool fresh = v;
+#pragma unroll
+                        for (int k = 0; k < o; ++k) fresh = fresh && !(u3[a][k] && t3[a][k] == t3[a][o]);
+                        u3[a][o] = fresh;
+                    }
                 }
 #pragma unroll
                 for (int iz = 0; iz < 4; ++iz)
 #pragma unroll
-                    for (int iy = 0; iy < 3; ++iy)
+                    for (int iy = 0; iy < 4; ++iy)
 #pragma unroll
-                        for (int ix = 0; ix < 3; ++ix)
-                            if (zv[iz] && yu[iy] && xu[ix])
-                                stamp[((int64_t)zt[iz] * tny + yt[iy]) * tnx + xt[ix]] = ctr;
+                        for (int ix = 0; ix < 4; ++ix)
+                            if (u3[2][iz] && u3[1][iy] && u3[0][ix])
+                                stamp[((int64_t)t3[2][iz] * tny + t3[1][iy]) * tnx + t3[0][ix]] = ctr;
             }
         }
         // stencil bounding box of the block (unwrapped cell indices)

@@ -12,7 +12,7 @@
 int main() {
     long cases = 0;
     for (int per = 0; per < 2; ++per)
-        for (int sh : {0, 1, 2, 4})
+        for (int sh : {0, 1, 2, 4, 5})
             for (int n = 1; n <= 70; ++n)
                 for (int lo = 0; lo < n; ++lo)
                     for (int span = 0; span <= 80; ++span) {

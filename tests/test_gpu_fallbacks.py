@@ -92,16 +92,19 @@ def _check_conditions(name, wl):
         assert len(q) <= NB  # one block
         assert np.prod(_stencil_extent(q)) > 3 * MAXP  # beyond the region and the FP32 stage
     elif name == "dense":
+        import paper_2604_17463_amd as P
         q = wl.droplets[0].nodes
+        box = wl.boxes[0]
         assert len(q) > SCAN_GROUP * NB
-        # nodes whose stencil touches each 16x4x1 band tile; more than
-        # 16 * 64 of them means more than 16 distinct blocks cover the tile
+        # nodes whose stencil touches each band tile; more than 16 * 64 of
+        # them means more than 16 distinct blocks cover the tile
+        sx, sy, sz = P.band_tile()
         b = np.floor(q - 0.5).astype(np.int64)
         o = np.arange(-1, 3)
-        tx = (b[:, 0, None] + o) % 32 // 16
-        ty = (b[:, 1, None] + o) % 36 // 4
-        tz = b[:, 2, None] + o + 2
-        ids = (tz[:, :, None, None] * 16 + ty[:, None, :, None]) * 2 + tx[:, None, None, :]
+        tx = (b[:, 0, None] + o) % box.nx // sx
+        ty = (b[:, 1, None] + o) % box.ny // sy
+        tz = (b[:, 2, None] + o + 2) // sz
+        ids = (tz[:, :, None, None] * 64 + ty[:, None, :, None]) * 64 + tx[:, None, None, :]
         ids = np.sort(ids.reshape(len(q), -1), axis=1)
         first = np.concatenate([np.ones((len(q), 1), bool), ids[:, 1:] != ids[:, :-1]], axis=1)
         assert np.bincount(ids[first]).max() > MAXC * NB
