@@ -14,7 +14,9 @@ import numpy as _np
 
 _HERE = _os.path.dirname(_os.path.abspath(__file__))
 _SRC = _os.path.join(_HERE, "iblb_oracle.c")
-_LIB = _os.path.join(_HERE, "liboracle.so")
+# IBLB_ORACLE_LIB names another build of iblb_oracle.c to load (the
+# sanitizer test loads an ASan/UBSan build through it)
+_LIB = _os.environ.get("IBLB_ORACLE_LIB") or _os.path.join(_HERE, "liboracle.so")
 
 
 def build(force: bool = True) -> str:
