@@ -98,9 +98,18 @@ def timed_steps(sim, steps):
 
 
 def band_cells(sim, b=0):
-    """Cells of the band tiles the node pass stamps at the current state."""
+    """Cells of the band tiles the node pass stamps at the current state
+    (edge tiles counted with their cells inside the box)."""
+    import numpy as np
+
+    import paper_2604_17463_amd as P
+    box = sim.wl.boxes[b]
+    tx, ty, tz = P.band_tile()
     _, flags = sim.compute_spread(b, want_F=False)
-    return int(flags.sum()) * 64
+    cz = np.minimum(tz, box.nz - tz * np.arange(flags.shape[0]))
+    cy = np.minimum(ty, box.ny - ty * np.arange(flags.shape[1]))
+    cx = np.minimum(tx, box.nx - tx * np.arange(flags.shape[2]))
+    return int((flags * cz[:, None, None] * cy[None, :, None] * cx[None, None, :]).sum())
 
 
 def oracle_errors(sim):

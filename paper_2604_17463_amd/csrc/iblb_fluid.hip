@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                     ++z;
                 }
             }
-            for (int x = tx; x < nx; x += BX) {
+            for (int x = rg.x0 + tx; x < rg.x1; x += BX) {
                 R g[CPT][Q];
                 const XOff xo = x_off<EB>(x, nx);
                 bool mine[CPT];

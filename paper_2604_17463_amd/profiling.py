@@ -115,6 +115,7 @@ def run_copy(gib, reps):
 def run_steps(name, n, launch=None, eager=False):
     import time
 
+    import numpy as np
     import torch
 
     import paper_2604_17463_amd as P
@@ -130,9 +131,14 @@ def run_steps(name, n, launch=None, eager=False):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     band = 0
-    for b in range(len(wl.boxes)):
+    tx, ty, tz = P.band_tile()
+    for b, box in enumerate(wl.boxes):
         _, flags_b = sim.compute_spread(b, want_F=False)
-        band += int(flags_b.sum()) * 64
+        # cells of the stamped tiles that lie in the box (edge tiles are partial)
+        cz = np.minimum(tz, box.nz - tz * np.arange(flags_b.shape[0]))
+        cy = np.minimum(ty, box.ny - ty * np.arange(flags_b.shape[1]))
+        cx = np.minimum(tx, box.nx - tx * np.arange(flags_b.shape[2]))
+        band += int((flags_b * cz[:, None, None] * cy[None, :, None] * cx[None, None, :]).sum())
     print(json.dumps({"workload": wl.name, "cells": wl.cells, "steps": n, "ms_per_step": dt / n * 1e3,
                       "launch": list(sim.get_launch()), "graph": not eager,
                       "band_cells_at_end": band}), flush=True)
