@@ -57,7 +57,7 @@ TRAFFIC = os.path.join(ROOT, "profiles", "bulk_collide_traffic.json")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("iblb_device.h", "iblb_fluid.hip", "iblb_internal.h"):
+    for f in ("iblb_device.h", "iblb_fluid.hip", "iblb_internal.h", "iblb_api.hip"):
         with open(os.path.join(ROOT, "paper_2604_17463_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -239,7 +239,9 @@ iblb_status build_plan(const iblb_config *cfg, Plan &p, std::string *err) {
         H.n_tiles = H.tnx * H.tny * H.tnz;
         H.tile_base = p.total_tiles;
         p.total_tiles += (int)round_up((size_t)H.n_tiles, TILE_CELLS);
-        p.max_rows += (size_t)B.ny * B.nz * ((B.nx + 63) / 64);  // row segments of at least 64 cells
+        // row segments of at least 64 cells, plus the empty row groups that
+        // fill the last group of eight
+        p.max_rows += ((size_t)B.ny * B.nz + 7) * ((B.nx + 63) / 64);
     }
     p.drops.resize(cfg->n_droplets);
     // droplets are laid out box by box so each box owns a contiguous block range
@@ -455,9 +457,23 @@ iblb_status upload_rows(iblb_ctx *c) {
         const iblb_box &B = c->plan.boxes[b].b;
         const int nr = B.ny * B.nz;
         const int seg = (BX % 64 == 0 && B.nx > BX) ? BX : B.nx;
-        for (int r = 0; r < nr; r += R)
+        if (seg == B.nx) {
+            for (int r = 0; r < nr; r += R) rows.push_back({b, r, std::min(r + R, nr), 0, B.nx, {0, 0, 0}});
+            continue;
+        }
+        // Rows split into segments: the segments of one row group share the
+        // cache lines at their ends (the +-1 shifted pulls, the periodic
+        // wrap), so they go to workgroups 8 apart, which the dispatcher
+        // places on the same XCD (one L2) at about the same time.  Groups of
+        // eight row groups, segment-major within a group; the last group is
+        // filled up with empty row groups so that the pattern holds for the
+        // whole box.
+        for (int r = 0; r < nr; r += 8 * R)
             for (int x0 = 0; x0 < B.nx; x0 += seg)
-                rows.push_back({b, r, std::min(r + R, nr), x0, std::min(x0 + seg, B.nx), {0, 0, 0}});
+                for (int k = 0; k < 8; ++k) {
+                    const int r0 = std::min(r + k * R, nr), r1 = std::min(r + (k + 1) * R, nr);
+                    rows.push_back({b, r0, r1, x0, std::min(x0 + seg, B.nx), {0, 0, 0}});
+                }
     }
     if (rows.size() > c->plan.max_rows)
         return set_err(c, IBLB_E_INVAL, "row table exceeds its reserved size");

@@ -296,6 +296,31 @@ def test_bulk_launch_configurations_give_identical_results(storage):
             assert np.array_equal(got[1], ref[1]), launch
 
 
+@pytest.mark.parametrize("storage", [F32, F16])
+def test_row_segments_give_identical_results(storage):
+    # rows longer than threads_x (a multiple of 64) are split into segments
+    # that workgroups eight apart take; 20 x 16 = 320 rows leave the last
+    # group of eight row groups partly empty for every rows-per-group value
+    # below; the 256-wide launch does not segment a 200-cell row
+    say("bulk row segments", storage)
+    v, t = mesh.sphere_above_wall(2, 4.5, 100.3, 10.2, 0.25)
+    wl = Workload("long-rows", [Box(200, 20, 16, tau=0.8)],
+                  [Droplet(0, v, t, sigma=0.01, theta_eq=math.radians(70), xi=0.25)], storage=storage)
+    ref = None
+    for launch in ((256, 1, 1, 0, 0), (64, 1, 1, 0, 0), (64, 2, 2, 1, 0), (128, 1, 2, 0, 3), (64, 4, 1, 1, 7),
+                   (128, 2, 1, 0, 0, 1), (64, 1, 1, 1, 8, 1)):
+        s = sim(wl, storage, flags=GRAPH)
+        s.set_launch(*launch)
+        s.step(30)
+        got = (s.read_state(0), s.read_nodes(0))
+        s.close()
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got[0], ref[0]), launch
+            assert np.array_equal(got[1], ref[1]), launch
+
+
 def _small_batch(seed=4):
     rng = np.random.default_rng(seed)
     boxes, drops = [], []
