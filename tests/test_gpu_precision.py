@@ -1,13 +1,25 @@
 """Precision workload (256x256x128 box, one 40,962-node sphere of radius 48
 relaxing toward 45 degrees, tau = 0.6 and 1.0) against the FP64 oracle's
-stored trace at 2,000 steps, for each population storage.
+stored trace, for each population storage, at step 2,000 and at the last
+step of the trace (the configured 10,000).
 
-FP64 and FP32 storage are held to the trace-parity bounds of the spreading
-run (height 1e-4, contact radius 1e-3, volume 1e-6, mass 1e-8 relative).
-FP16 and BF16 deviation storage carry their own rounding (11 and 8
-significant bits of each stored deviation, FP32 arithmetic); their errors
-are reported, and bounded only loosely (height 1e-3, contact radius 2e-2,
-volume 1e-4, mass 1e-5), so that a broken conversion still fails.
+- FP64 storage is held to 1e-9 relative on every observable at both steps:
+  only the order of rounding differs from the oracle.
+- FP32 storage is held to the trace-parity bounds of the spreading run
+  (height 1e-4, contact radius 1e-3, volume 1e-6, mass 1e-8 relative).
+- FP16 and BF16 deviation storage carry their own rounding (11 and 8
+  significant bits of each stored deviation, FP32 arithmetic); their errors
+  are bounded only loosely (height 1e-3, contact radius 2e-2, volume 1e-4,
+  mass 1e-5), so that a broken conversion still fails.
+
+The height is the one observable that changes quickly late in the tau = 0.6
+run: the apex falls by about 0.02 lattice units per step near step 10,000,
+so a run that is a fraction of a step ahead of or behind the oracle's
+trajectory differs from it in height by more than the bounds above.  After
+step 2,000 the height may therefore also differ by the height change of a
+few steps at the trace's own rate there (from its last two rows): 2 steps
+for FP32 and FP16, 200 for BF16 (2 % of the run).  The contact radius,
+volume and mass are held to the bounds above throughout.
 """
 import json
 import os
@@ -21,8 +33,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.join(HERE, "golden"))
 
 KEYS = ("height", "contact_radius", "volume", "mass")
+FP64 = {k: 1e-9 for k in KEYS}
 TIGHT = {"height": 1e-4, "contact_radius": 1e-3, "volume": 1e-6, "mass": 1e-8}
 LOOSE = {"height": 1e-3, "contact_radius": 2e-2, "volume": 1e-4, "mass": 1e-5}
+FIRST = 2000
+# steps of the trace's late height change a run may lead or trail by
+PHASE = {"f64": 0, "f32": 2, "f16dev": 2, "bf16dev": 200}
 
 
 @pytest.mark.gpu
@@ -34,23 +50,32 @@ def test_precision_workload_against_oracle_trace(tau):
 
     with open(os.path.join(HERE, "golden", f"precision_trace_oracle_tau{tau:g}.json")) as fh:
         tr = json.load(fh)
-    steps = tr["steps"]
+    steps, every = tr["steps"], tr["every"]
     wl = configs.precision_c3(tau=tau, steps=steps)
     assert tr["workload_sha256"] == workload_hash(wl), "stored trace is of another workload"
-    ref = {r["step"]: r for r in tr["rows"]}[steps]
+    rows = {r["step"]: r for r in tr["rows"]}
+    checks = sorted({min(FIRST, steps), steps})
     report = {}
-    for storage, name, bound in ((P.IBLB_F64, "f64", TIGHT), (P.IBLB_F32, "f32", TIGHT),
+    for storage, name, bound in ((P.IBLB_F64, "f64", FP64), (P.IBLB_F32, "f32", TIGHT),
                                  (P.IBLB_F16DEV, "f16dev", LOOSE), (P.IBLB_BF16DEV, "bf16dev", LOOSE)):
-        say(f"precision workload tau {tau}: {name}, {steps} steps")
+        say(f"precision workload tau {tau}: {name}, steps {checks}")
         sim = P.Simulation(wl, storage=storage, flags=P.IBLB_FLAG_GRAPH,
                            dev_scale=4096.0 if storage == P.IBLB_F16DEV else 1.0)
-        sim.step(steps)
-        d, b = sim.observables()
+        done = 0
+        for n in checks:
+            sim.step(n - done)
+            done = n
+            d, b = sim.observables()
+            got = {"height": d[0]["height"], "contact_radius": d[0]["contact_radius"],
+                   "volume": d[0]["volume"], "mass": b[0]["mass"]}
+            ref = rows[n]
+            err = {k: abs(got[k] - ref[k]) / abs(ref[k]) for k in KEYS}
+            report[f"{name}@{n}"] = err
+            for k in KEYS:
+                allowed = bound[k]
+                if k == "height" and n > FIRST:
+                    rate = abs(ref["height"] - rows[n - every]["height"]) / every
+                    allowed = max(allowed, PHASE[name] * rate / abs(ref["height"]))
+                assert err[k] <= allowed, f"{name} step {n} {k}: {err[k]:.3e} > {allowed:.1e}"
         sim.close()
-        got = {"height": d[0]["height"], "contact_radius": d[0]["contact_radius"],
-               "volume": d[0]["volume"], "mass": b[0]["mass"]}
-        err = {k: abs(got[k] - ref[k]) / abs(ref[k]) for k in KEYS}
-        report[name] = err
-        for k in KEYS:
-            assert err[k] <= bound[k], f"{name} {k}: {err[k]:.3e} > {bound[k]:.0e}"
     say("relative errors vs oracle: " + json.dumps(report))
