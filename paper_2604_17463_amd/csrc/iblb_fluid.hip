@@ -302,6 +302,9 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
 }
 
 // ------------------------------------------------------------------- band
+// Largest band grid (workgroups of four waves, one wave per listed tile);
+// a multiple of eight.
+constexpr int BAND_GRID = 8192;
 // One wavefront per stamped tile of this epoch, one lane per cell: gather
 // the spread force, then (COLLIDE) pull, collide with F = body force +
 // spread force, store the populations (the bulk kernel leaves these cells
@@ -310,7 +313,8 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
 // ONE_BOX: a single box, whose descriptor is read beside the list entry
 // rather than after it.
 template <int ST, bool COLLIDE, bool ONE_BOX>
-__global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u, float scale, float inv) {
+__global__ void __launch_bounds__(256)
+    k_band(DevPtrs P, int parity, int full_u, float scale, float inv, int xcd) {
     using S = Stor<ST>;
     using R = typename S::R;
     constexpr uint32_t EB = sizeof(typename S::T);
@@ -343,10 +347,23 @@ __global__ void __launch_bounds__(256) k_band(DevPtrs P, int parity, int full_u,
                  "s"(g0.tnx), "s"(g0.tny), "s"(g0.nx), "s"(g0.ny), "s"(g0.nz), "s"(g0.sx), "s"(g0.zbc),
                  "s"(g0.plane), "s"(g0.src));
     const int count = min((ctr & 1) ? n1 : n0, P.total_tiles);
-    for (int i = wave; i < count; i += nwaves) {
+    // list positions of this wave: every nwaves-th from its index, or (xcd,
+    // a grid of whole groups of eight workgroups) a contiguous eighth of the
+    // list per XCD, so that neighbouring tiles, which read the same partial
+    // regions and share population lines, are taken on one L2 at about the
+    // same time
+    int i0 = wave, i1 = count, di = nwaves;
+    if (xcd) {
+        const int x = blockIdx.x & 7;
+        i0 = (int)((int64_t)count * x / 8) + (blockIdx.x >> 3) * 4 + (threadIdx.x >> 6);
+        i0 = __builtin_amdgcn_readfirstlane(i0);
+        i1 = (int)((int64_t)count * (x + 1) / 8);
+        di = nwaves / 8;
+    }
+    for (int i = i0; i < i1; i += di) {
         // global tile id and its box
-        const int gt = i == wave ? first_gt : tl[2 * i];
-        const int box = ONE_BOX ? 0 : (i == wave ? first_box : tl[2 * i + 1]);
+        const int gt = (!xcd && i == wave) ? first_gt : tl[2 * i];
+        const int box = ONE_BOX ? 0 : ((!xcd && i == wave) ? first_box : tl[2 * i + 1]);
         const IBLB_CONST BoxDev *B = (const IBLB_CONST BoxDev *)P.boxes + box;
         const Geo G = ONE_BOX ? g0 : geo(B);
         const int lt = gt - G.tile_base;
@@ -561,13 +578,17 @@ template <int ST, bool C>
 static void launch_band_t(const DevPtrs &P, int parity, int full_u, float scale, hipStream_t s) {
     // one wave per tile up to 32,768 waves (workgroups of four); large
     // bands (many boxes or droplets) loop over the rest of the list
-    const int grid = min((P.total_tiles + 3) / 4, 8192);
+    const int grid = min((P.total_tiles + 3) / 4, BAND_GRID);
+    // a full grid (a multiple of eight workgroups) takes the list in XCD
+    // ranges; a small one keeps the interleaved order, whose first entry
+    // loads beside the list count (latency decides there)
+    const int xcd = grid == BAND_GRID ? 1 : 0;
     if (P.n_boxes == 1)
         hipLaunchKernelGGL((k_band<ST, C, true>), dim3(grid), dim3(256), 0, s, P, parity, full_u, scale,
-                           1.0f / scale);
+                           1.0f / scale, xcd);
     else
         hipLaunchKernelGGL((k_band<ST, C, false>), dim3(grid), dim3(256), 0, s, P, parity, full_u, scale,
-                           1.0f / scale);
+                           1.0f / scale, xcd);
 }
 
 hipError_t launch_band(const DevPtrs &P, int storage, int parity, int full_u, float scale, bool collide,

@@ -18,7 +18,8 @@ namespace iblb {
 template <typename R>
 __global__ void __launch_bounds__(256) k_tri(DevPtrs P) {
     __shared__ double sv[256], sa[256];
-    const TriChunk ch = P.chunks[blockIdx.x];
+    const int ci = xcd_item(blockIdx.x, gridDim.x);
+    const TriChunk ch = P.chunks[ci];
     const DropDev &D = P.drops[ch.drop];
     const R *qh = (const R *)P.qh, *ql = (const R *)P.ql;
     const int t = ch.t0 + threadIdx.x;
@@ -81,8 +82,8 @@ __global__ void __launch_bounds__(256) k_tri(DevPtrs P) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        P.tri_part[blockIdx.x] = sv[0];
-        P.tri_part[P.n_chunks + blockIdx.x] = sa[0];
+        P.tri_part[ci] = sv[0];
+        P.tri_part[P.n_chunks + ci] = sa[0];
     }
 }
 
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode, int parit
     __shared__ int sreg[5];  // ex, ey, ez, overflow, nodes in the block
     __shared__ int tlist[3][64];  // distinct tiles per axis of the block's stencil box
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int blk = blockIdx.x;
+    const int blk = xcd_item(blockIdx.x, gridDim.x);
     // droplet and box in one load, so their records load side by side
     const int d = P.blk_drop[2 * blk], bi = P.blk_drop[2 * blk + 1];
     const DropDev &D = P.drops[d];
@@ -456,7 +457,7 @@ __global__ void __launch_bounds__(256) k_interp(DevPtrs P, int mode, double *Uou
     __shared__ R su[3 * MAXR];
     __shared__ R red[3][3][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int blk = blockIdx.x;
+    const int blk = xcd_item(blockIdx.x, gridDim.x);
     const DropDev &D = P.drops[P.blk_drop[2 * blk]];
     const BoxDev &B = P.boxes[P.blk_drop[2 * blk + 1]];
     const int N = P.Ntot, nb = P.nblk;
