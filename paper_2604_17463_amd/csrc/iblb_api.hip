@@ -54,7 +54,7 @@ thread_local std::string g_last_error = "no error";
 
 constexpr size_t ALIGN = 256;
 constexpr size_t BIG_ALIGN = 2u << 20;
-constexpr int MULTI = 8;          // steps per multi-step graph
+constexpr int MULTI = 32;         // steps per multi-step graph
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

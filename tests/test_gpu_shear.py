@@ -167,7 +167,7 @@ def test_free_droplet_in_shear_reaches_taylor_deformation(lam, perm):
 
 
 def test_moving_walls_graph_replay_is_bitwise_equal_to_eager():
-    # 37 steps: one single-step graph, four eight-step graphs, four single steps
+    # 37 steps: one single-step graph, one 32-step graph, four single steps
     say("moving walls graph vs eager")
     wl = configs.shear_droplet(lam=2.0, r=6.0, ca=0.2, re=0.5, shape=(32, 24, 32), level=3,
                                storage=F32)
