@@ -53,17 +53,6 @@ template <> struct Stor<3> {  // bfloat16 deviations
     static __device__ __forceinline__ void put_nt(IBLB_GLOBAL T *p, R v) { __builtin_nontemporal_store((T)v, p); }
 };
 
-// Item of workgroup w when a launch of n workgroups takes n items (node
-// blocks, triangle chunks) in order: the dispatcher hands workgroups to the
-// eight XCDs in turn (w on XCD w % 8), and this gives each XCD one
-// contiguous range of items, so that neighbouring blocks, whose stencil
-// regions and incident triangles overlap, share one L2.  A bijection of
-// [0, n): XCD x takes [x q + min(x, r), ...) with q = n / 8, r = n % 8.
-__device__ __forceinline__ int xcd_item(int w, int n) {
-    const int x = w & 7, q = n >> 3, r = n & 7;
-    return x * q + min(x, r) + (w >> 3);
-}
-
 __device__ __forceinline__ int wrapn(int i, int n) {
     int r = i % n;
     return r < 0 ? r + n : r;

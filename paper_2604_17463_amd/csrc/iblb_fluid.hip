@@ -354,11 +354,10 @@ __global__ void __launch_bounds__(256)
     // same time
     int i0 = wave, i1 = count, di = nwaves;
     if (xcd) {
-        const int x = blockIdx.x & 7;
-        i0 = (int)((int64_t)count * x / 8) + (blockIdx.x >> 3) * 4 + (threadIdx.x >> 6);
-        i0 = __builtin_amdgcn_readfirstlane(i0);
-        i1 = (int)((int64_t)count * (x + 1) / 8);
-        di = nwaves / 8;
+        const ListRange lr = xcd_list_range(blockIdx.x, threadIdx.x >> 6, gridDim.x, count);
+        i0 = __builtin_amdgcn_readfirstlane(lr.first);
+        i1 = lr.end;
+        di = lr.stride;
     }
     for (int i = i0; i < i1; i += di) {
         // global tile id and its box

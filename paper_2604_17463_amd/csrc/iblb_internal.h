@@ -78,6 +78,30 @@ __host__ __device__ inline TileRun tile_run(int lo, int span, int n, int sh, boo
     return {t0, nt - t0 + t1 + 1};
 }
 
+// Item of workgroup w when a launch of n workgroups takes n items (node
+// blocks, triangle chunks) in order: the dispatcher hands workgroups to the
+// eight XCDs in turn (w on XCD w % 8), and this gives each XCD one
+// contiguous range of items, so that neighbouring blocks, whose stencil
+// regions and incident triangles overlap, share one L2.  A bijection of
+// [0, n): XCD x takes [x q + min(x, r), ...) with q = n / 8, r = n % 8.
+__host__ __device__ inline int xcd_item(int w, int n) {
+    const int x = w & 7, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + (w >> 3);
+}
+
+// List positions of wave v (0..3) of workgroup b when a grid of g
+// workgroups (a multiple of eight) takes a list of `count` entries: the
+// workgroups of XCD b % 8 share one contiguous eighth of the list, each
+// wave taking every (g / 2)-th position of it from its own start.
+struct ListRange {
+    int first, end, stride;
+};
+__host__ __device__ inline ListRange xcd_list_range(int b, int v, int g, int count) {
+    const int x = b & 7;
+    const int lo = (int)((int64_t)count * x / 8), hi = (int)((int64_t)count * (x + 1) / 8);
+    return {lo + (b >> 3) * 4 + v, hi, g / 2};
+}
+
 // Velocity set in the library's order: 0 = rest, i and i+9 opposite (i=1..9).
 __host__ __device__ constexpr int cx_of(int i) {
     constexpr int t[Q] = {0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
