@@ -189,10 +189,10 @@ __device__ __forceinline__ void gather_F(const DevPtrs &P, const IBLB_CONST BoxD
                     if (zper && dz < 0) dz += nz;
                     const int ex = br[3], ey = br[4], ez = br[5];
                     if (dx < ex && dy < ey && dz >= 0 && dz < ez) {
-                        const int64_t c = (int64_t)blk * 3 * MAXP + (dz * ey + dy) * ex + dx;
+                        const int64_t c = (int64_t)blk * 3 * MAXP + 3 * ((dz * ey + dy) * ex + dx);
                         v[k][0] = part[c];
-                        v[k][1] = part[c + MAXP];
-                        v[k][2] = part[c + 2 * MAXP];
+                        v[k][1] = part[c + 1];
+                        v[k][2] = part[c + 2];
                     }
                 }
             }

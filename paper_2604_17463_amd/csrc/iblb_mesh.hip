@@ -400,7 +400,9 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode, int parit
         }
     }
     __syncthreads();
-    // block partial = region 0 + region 1 + ... (fixed order)
+    // block partial = region 0 + region 1 + ... (fixed order), written with
+    // the three components of a cell side by side: the band gather reads a
+    // run of a region row as one contiguous stretch of lines
     IBLB_GLOBAL R *out = (IBLB_GLOBAL R *)P.part + (int64_t)blk * 3 * MAXP;
     for (int c = tid; c < ncell; c += NT)
 #pragma unroll
@@ -408,7 +410,7 @@ __global__ void __launch_bounds__(64 * NR) k_node(DevPtrs P, int mode, int parit
             R v = reg[0][k * MAXP + c];
 #pragma unroll
             for (int r = 1; r < NR; ++r) v += reg[r][k * MAXP + c];
-            out[k * MAXP + c] = v;
+            out[3 * c + k] = v;
         }
 }
 
