@@ -307,7 +307,9 @@ iblb_status iblb_load_state(struct iblb_ctx *ctx, const void *blob, size_t bytes
 
 /* Launch configuration of the fused stream-collide kernel and the step
  * schedule:
- *   threads_x         threads along x per row, a multiple of 32;
+ *   threads_x         threads along x per row, a multiple of 32 (when a
+ *                     multiple of 64, rows longer than threads_x cells are
+ *                     split into segments of that length, one per workgroup);
  *   rows_per_group    rows of a workgroup; threads_x * rows_per_group must be
  *                     a multiple of 64 and at most 256;
  *   cells_per_thread  1 or 2 rows handled by a thread at a time (their loads

@@ -12,9 +12,11 @@ namespace iblb {
 // Every cell of every box with F = body force, except (SKIP) the cells of
 // the band tiles this step's node pass stamped: the band kernel owns those
 // (it adds the spread force) and runs beside this kernel, so each cell is
-// pulled, collided and stored once per step.  A workgroup takes whole x-rows
-// (a row group); threads stride along x so the +-1 shifted loads of a row
-// stay inside one workgroup.  UROW: each wavefront lies in one row
+// pulled, collided and stored once per step.  A workgroup takes a row group
+// (rows, or one segment of threads_x cells of rows longer than that; the
+// segments of a row go to workgroups on one XCD, so the lines at their ends
+// are fetched once); threads stride along x so the +-1 shifted loads of a
+// row stay inside the workgroup or its XCD.  UROW: each wavefront lies in one row
 // (threads_x a multiple of 64), so the row addressing is wave-uniform and
 // lives in scalar registers.  NT: the populations are written with
 // streaming stores (they are read again only in the next step; pays off
@@ -311,7 +313,8 @@ constexpr int BAND_GRID = 8192;
 // alone) and write u to the band; or (!COLLIDE, inspection) store F in the
 // band.
 // ONE_BOX: a single box, whose descriptor is read beside the list entry
-// rather than after it.
+// rather than after it.  xcd: the grid (BAND_GRID workgroups) takes the
+// list in one contiguous eighth per XCD instead of interleaved.
 template <int ST, bool COLLIDE, bool ONE_BOX>
 __global__ void __launch_bounds__(256)
     k_band(DevPtrs P, int parity, int full_u, float scale, float inv, int xcd) {
