@@ -456,9 +456,14 @@ iblb_status upload_rows(iblb_ctx *c) {
     for (int b = 0; b < (int)c->plan.boxes.size(); ++b) {
         const iblb_box &B = c->plan.boxes[b].b;
         const int nr = B.ny * B.nz;
+        // rows end in the padding (zeros written with the row's last line,
+        // so that no line is written in part) when it is at most an eighth
+        // of the row: 250 -> 256 cells 10 % faster, 48 -> 64 slower
+        const int sx = c->plan.boxes[b].sx;
+        const int xe = (sx - B.nx) * 8 <= B.nx ? sx : B.nx;
         const int seg = (BX % 64 == 0 && B.nx > BX) ? BX : B.nx;
         if (seg == B.nx) {
-            for (int r = 0; r < nr; r += R) rows.push_back({b, r, std::min(r + R, nr), 0, B.nx, {0, 0, 0}});
+            for (int r = 0; r < nr; r += R) rows.push_back({b, r, std::min(r + R, nr), 0, xe, {0, 0, 0}});
             continue;
         }
         // Rows split into segments: the segments of one row group share the
@@ -472,7 +477,7 @@ iblb_status upload_rows(iblb_ctx *c) {
             for (int x0 = 0; x0 < B.nx; x0 += seg)
                 for (int k = 0; k < 8; ++k) {
                     const int r0 = std::min(r + k * R, nr), r1 = std::min(r + (k + 1) * R, nr);
-                    rows.push_back({b, r0, r1, x0, std::min(x0 + seg, B.nx), {0, 0, 0}});
+                    rows.push_back({b, r0, r1, x0, x0 + seg < B.nx ? x0 + seg : xe, {0, 0, 0}});
                 }
     }
     if (rows.size() > c->plan.max_rows)

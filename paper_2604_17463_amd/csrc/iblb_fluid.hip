@@ -84,15 +84,25 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                     ++z;
                 }
             }
+            // A row group whose x range reaches into the row's padding
+            // (x1 > nx: the row table asks for it where the padding is a
+            // small part of the row): the lanes x in [nx, sx) redo the row's
+            // last cell and store zeros (the padding's value since init) in
+            // the same store instructions as their neighbours, so that every
+            // line of the row is written whole (a line written in part made
+            // rows of 250 cells 10 % slower than rows of 256)
             for (int x = rg.x0 + tx; x < rg.x1; x += BX) {
                 R g[CPT][Q];
-                const XOff xo = x_off<EB>(x, nx);
+                const bool pad = x >= nx;
+                const int xs = pad ? nx - 1 : x;  // the cell computed
+                const XOff xo = x_off<EB>(xs, nx);
+                const uint32_t xst = (uint32_t)x * EB;  // the cell stored
                 bool mine[CPT];
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
                     mine[k] = on[k];
                     if (skip_box && on[k])
-                        mine[k] = stamp[((int64_t)(rzk[k] >> TZS) * tny + (ryk[k] >> TYS)) * tnx + (x >> TXS)] != epoch;
+                        mine[k] = stamp[((int64_t)(rzk[k] >> TZS) * tny + (ryk[k] >> TYS)) * tnx + (xs >> TXS)] != epoch;
                 }
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
@@ -106,23 +116,26 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                 for (int k = 0; k < CPT; ++k) {
                     if (!mine[k]) continue;
                     R out[Q], u[3], rho;
-                    const uint32_t own = ra[k].ro[1][1] + xo.c;
+                    const uint32_t own = ra[k].ro[1][1] + xst;
                     R om = omega, gu = guo;
                     if (EXT && moving && (ra[k].wlo || ra[k].whi)) wall_shift<R>(g[k], ra[k].wlo, ra[k].whi, kw);
                     if (EXT && contrast) {
                         // this step's inside bits (computed by the mesh
                         // chain, which this kernel follows)
-                        const uint64_t w = mask[((int64_t)(rzk[k] >> 6) * ny + ryk[k]) * nx + x];
+                        const uint64_t w = mask[((int64_t)(rzk[k] >> 6) * ny + ryk[k]) * nx + xs];
                         if ((w >> (rzk[k] & 63)) & 1ull) {
                             om = omega_in;
                             gu = guo_in;
                         }
                     }
                     collide<ST>(g[k], gx, gy, gz, rho0, om, gu, scale, inv, out, u, rho);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) out[i] = pad ? R(0) : out[i];
                     if constexpr (BUF)
-                        store_buf<ST, NT>(rd, (uint32_t)pb, ra[k].ro[1][1], xo.c, out);
+                        store_buf<ST, NT>(rd, (uint32_t)pb, ra[k].ro[1][1], xst, out);
                     else
                         store_ptr<ST, NT>(dst, pb, own, out);
+                    if (pad) continue;
                     if (full_u) {
                         const uint64_t e = own / EB;
                         uf[e] = u[0];

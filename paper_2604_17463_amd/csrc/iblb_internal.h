@@ -161,7 +161,7 @@ struct DropDev {
 
 struct RowGroup {
     int32_t box, r0, r1;        // rows r = z*ny + y in [r0, r1)
-    int32_t x0, x1;             // cells x0 <= x < x1 of those rows
+    int32_t x0, x1;             // cells x0 <= x < x1 of those rows (x1 > nx: the padding too)
     int32_t pad[3];
 };
 
