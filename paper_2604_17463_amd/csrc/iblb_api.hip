@@ -483,6 +483,9 @@ iblb_status upload_rows(iblb_ctx *c) {
     if (rows.size() > c->plan.max_rows)
         return set_err(c, IBLB_E_INVAL, "row table exceeds its reserved size");
     c->P.n_rowgroups = (int)rows.size();
+    c->P.pad_rows = 0;
+    for (const RowGroup &g : rows)
+        if (g.x1 > c->plan.boxes[g.box].b.nx) c->P.pad_rows = 1;
     c->L.grid = (int)rows.size();
     if (c->L.maxg > 0 && c->L.maxg < c->L.grid) c->L.grid = c->L.maxg;
     HIPCHK(c, hipMemcpyAsync(c->P.rows, rows.data(), rows.size() * sizeof(RowGroup),

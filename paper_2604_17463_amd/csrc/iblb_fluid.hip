@@ -24,7 +24,7 @@ namespace iblb {
 // box has a viscosity contrast or a moving wall (the plain variant carries
 // none of their registers).  Without SKIP the kernel is the plain
 // stream-collide of every cell (boxes without droplets, timing).
-template <int ST, bool UROW, bool NT, int CPT, bool EXT, bool SKIP>
+template <int ST, bool UROW, bool NT, int CPT, bool EXT, bool SKIP, bool PADW>
 __global__ void __launch_bounds__(K1_MAX_THREADS)
     k_bulk(DevPtrs P, int parity, int full_u, float scale, float inv) {
     using S = Stor<ST>;
@@ -84,19 +84,20 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                     ++z;
                 }
             }
-            // A row group whose x range reaches into the row's padding
+            // PADW: some row group's x range reaches into its row's padding
             // (x1 > nx: the row table asks for it where the padding is a
             // small part of the row): the lanes x in [nx, sx) redo the row's
             // last cell and store zeros (the padding's value since init) in
             // the same store instructions as their neighbours, so that every
             // line of the row is written whole (a line written in part made
-            // rows of 250 cells 10 % slower than rows of 256)
+            // rows of 250 cells 10 % slower than rows of 256).  A separate
+            // instantiation, so that workloads without it carry none of it.
             for (int x = rg.x0 + tx; x < rg.x1; x += BX) {
                 R g[CPT][Q];
-                const bool pad = x >= nx;
+                const bool pad = PADW && x >= nx;
                 const int xs = pad ? nx - 1 : x;  // the cell computed
                 const XOff xo = x_off<EB>(xs, nx);
-                const uint32_t xst = (uint32_t)x * EB;  // the cell stored
+                const uint32_t xst = PADW ? (uint32_t)x * EB : xo.c;  // the cell stored
                 bool mine[CPT];
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
@@ -129,13 +130,15 @@ __global__ void __launch_bounds__(K1_MAX_THREADS)
                         }
                     }
                     collide<ST>(g[k], gx, gy, gz, rho0, om, gu, scale, inv, out, u, rho);
+                    if constexpr (PADW) {
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) out[i] = pad ? R(0) : out[i];
+                        for (int i = 0; i < Q; ++i) out[i] = pad ? R(0) : out[i];
+                    }
                     if constexpr (BUF)
                         store_buf<ST, NT>(rd, (uint32_t)pb, ra[k].ro[1][1], xst, out);
                     else
                         store_ptr<ST, NT>(dst, pb, own, out);
-                    if (pad) continue;
+                    if (PADW && pad) continue;
                     if (full_u) {
                         const uint64_t e = own / EB;
                         uf[e] = u[0];
@@ -535,19 +538,32 @@ __global__ void __launch_bounds__(256) k_box_obs_final(DevPtrs P, int box, int g
 }
 
 // ---------------------------------------------------------------- launchers
-template <int ST, bool UROW, bool NT, bool SKIP>
-static void launch_bulk_c(const DevPtrs &P, int parity, int full_u, float scale, float inv, const Launch &L,
+template <int ST, bool UROW, bool NT, bool SKIP, bool PADW>
+static void launch_bulk_p(const DevPtrs &P, int parity, int full_u, float scale, float inv, const Launch &L,
                           dim3 grid, dim3 block, hipStream_t s) {
     if (P.contrast || P.moving) {
         if (UROW && L.cpt == 2)
-            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, true, SKIP>), grid, block, 0, s, P, parity, full_u, scale, inv);
+            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, true, SKIP, PADW>), grid, block, 0, s, P, parity, full_u,
+                               scale, inv);
         else
-            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, true, SKIP>), grid, block, 0, s, P, parity, full_u, scale, inv);
+            hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, true, SKIP, PADW>), grid, block, 0, s, P, parity, full_u,
+                               scale, inv);
     } else if (UROW && L.cpt == 2) {
-        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, false, SKIP>), grid, block, 0, s, P, parity, full_u, scale, inv);
+        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 2, false, SKIP, PADW>), grid, block, 0, s, P, parity, full_u, scale,
+                           inv);
     } else {
-        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, false, SKIP>), grid, block, 0, s, P, parity, full_u, scale, inv);
+        hipLaunchKernelGGL((k_bulk<ST, UROW, NT, 1, false, SKIP, PADW>), grid, block, 0, s, P, parity, full_u, scale,
+                           inv);
     }
+}
+
+template <int ST, bool UROW, bool NT, bool SKIP>
+static void launch_bulk_c(const DevPtrs &P, int parity, int full_u, float scale, float inv, const Launch &L,
+                          dim3 grid, dim3 block, hipStream_t s) {
+    if (P.pad_rows)
+        launch_bulk_p<ST, UROW, NT, SKIP, true>(P, parity, full_u, scale, inv, L, grid, block, s);
+    else
+        launch_bulk_p<ST, UROW, NT, SKIP, false>(P, parity, full_u, scale, inv, L, grid, block, s);
 }
 
 template <int ST, bool SKIP>

@@ -206,6 +206,7 @@ struct DevPtrs {
     int32_t contrast;           // some box has tau_in set
     int32_t moving;             // some box has a moving wall
     int32_t mask_words;         // largest nzw*ny*nx over those boxes
+    int32_t pad_rows;           // some row group runs into its row's padding (x1 > nx)
 };
 
 // Launch entry points (iblb_fluid.hip, iblb_mesh.hip).
