@@ -314,9 +314,10 @@ iblb_status iblb_load_state(struct iblb_ctx *ctx, const void *blob, size_t bytes
  *                     a multiple of 64 and at most 256;
  *   cells_per_thread  1 or 2 rows handled by a thread at a time (their loads
  *                     issued together); 2 needs threads_x a multiple of 64;
- *   streaming_stores  0 or 1: write the populations with non-temporal stores
- *                     (helps once the two population buffers exceed the GPU's
- *                     last-level cache, hurts while they fit);
+ *   streaming_stores  0 or 1: write the populations with non-temporal stores,
+ *                     in the stream-collide and the band kernel (helps once
+ *                     the two population buffers exceed the GPU's last-level
+ *                     cache, hurts while they fit);
  *   max_workgroups    0, or a cap on the grid: the workgroups then loop over
  *                     the rows, leaving compute units to the mesh kernels that
  *                     run beside the stream-collide;

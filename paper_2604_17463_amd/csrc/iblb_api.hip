@@ -556,7 +556,7 @@ iblb_status enqueue_steps(iblb_ctx *c, hipStream_t s, int parity, bool advect_fi
             if (st != IBLB_OK) return st;
             HIPCHK(c, launch_bulk(c->P, c->plan.storage, p, full_u, scale, c->L, false, s));
             HIPCHK(c, hipStreamWaitEvent(s, c->ev_chain, 0));
-            HIPCHK(c, launch_band(c->P, c->plan.storage, p, full_u, scale, true, s));
+            HIPCHK(c, launch_band(c->P, c->plan.storage, p, full_u, scale, true, c->L.nt, s));
         }
         return IBLB_OK;
     }
@@ -569,7 +569,7 @@ iblb_status enqueue_steps(iblb_ctx *c, hipStream_t s, int parity, bool advect_fi
         HIPCHK(c, hipStreamWaitEvent(s, c->ev_chain, 0));
         HIPCHK(c, launch_bulk(c->P, c->plan.storage, p, full_u, scale, c->L, true, s));
         if (k > 0) HIPCHK(c, hipStreamWaitEvent(c->ib, c->ev_bulk, 0));  // the previous step's bulk kernel
-        HIPCHK(c, launch_band(c->P, c->plan.storage, p, full_u, scale, true, c->ib));
+        HIPCHK(c, launch_band(c->P, c->plan.storage, p, full_u, scale, true, c->L.nt, c->ib));
         HIPCHK(c, hipEventRecord(c->ev_bulk, s));
     }
     HIPCHK(c, hipEventRecord(c->ev_join, c->ib));
@@ -1330,7 +1330,7 @@ iblb_status iblb_step_static(iblb_ctx *c, int64_t n) {
         if (st != IBLB_OK) return st;
         HIPCHK(c, launch_tri(V, f64, s));
         HIPCHK(c, launch_node(V, f64, 0, par, s));
-        HIPCHK(c, launch_band(V, p.storage, par, full_u, scale, true, s));
+        HIPCHK(c, launch_band(V, p.storage, par, full_u, scale, true, c->L.nt, s));
         HIPCHK(c, launch_bulk(V, p.storage, par, full_u, scale, c->L, true, s));
         HIPCHK(c, launch_interp(V, f64, 0, nullptr, s));
         c->last_step_epoch = c->epoch;
@@ -1656,7 +1656,7 @@ iblb_status iblb_compute_spread(iblb_ctx *c, int32_t b, double *F_out, uint8_t *
     const bool f64 = is_f64(c);
     HIPCHK(c, launch_tri(c->P, f64, c->stream));
     HIPCHK(c, launch_node(c->P, f64, 0, c->parity, c->stream));
-    HIPCHK(c, launch_band(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, false, c->stream));
+    HIPCHK(c, launch_band(c->P, c->plan.storage, c->parity, 0, (float)c->plan.scale, false, 0, c->stream));
     HIPCHK(c, launch_epoch(c->P, c->stream));
     const int32_t used = c->epoch;
     ++c->epoch;

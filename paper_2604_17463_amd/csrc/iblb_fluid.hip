@@ -333,7 +333,7 @@ constexpr int BAND_GRID = 8192;
 // list in one contiguous eighth per XCD instead of interleaved.
 template <int ST, bool COLLIDE, bool ONE_BOX>
 __global__ void __launch_bounds__(256)
-    k_band(DevPtrs P, int parity, int full_u, float scale, float inv, int xcd) {
+    k_band(DevPtrs P, int parity, int full_u, float scale, float inv, int xcd, int nt) {
     using S = Stor<ST>;
     using R = typename S::R;
     constexpr uint32_t EB = sizeof(typename S::T);
@@ -433,7 +433,12 @@ __global__ void __launch_bounds__(256)
         }
         collide<ST>(g, (R)B->g[0] + F0, (R)B->g[1] + F1, (R)B->g[2] + F2, (R)B->rho0, om, gu, scale, inv,
                     out, u, rho);
-        store_buf<ST, false, true>(pop_res(B->f[parity ^ 1], pb), (uint32_t)pb, ra.ro[1][1], xo.c, out);
+        // streaming stores where the bulk kernel uses them (the populations
+        // exceed the last-level cache)
+        if (nt)
+            store_buf<ST, true, true>(pop_res(B->f[parity ^ 1], pb), (uint32_t)pb, ra.ro[1][1], xo.c, out);
+        else
+            store_buf<ST, false, true>(pop_res(B->f[parity ^ 1], pb), (uint32_t)pb, ra.ro[1][1], xo.c, out);
         IBLB_GLOBAL R *ub = (IBLB_GLOBAL R *)B->uband + (int64_t)lt * 3 * TILE_CELLS;
         ub[lane] = u[0];
         ub[TILE_CELLS + lane] = u[1];
@@ -606,7 +611,7 @@ hipError_t launch_bulk(const DevPtrs &P, int storage, int parity, int full_u, fl
 }
 
 template <int ST, bool C>
-static void launch_band_t(const DevPtrs &P, int parity, int full_u, float scale, hipStream_t s) {
+static void launch_band_t(const DevPtrs &P, int parity, int full_u, float scale, int nt, hipStream_t s) {
     // one wave per tile up to 32,768 waves (workgroups of four); large
     // bands (many boxes or droplets) loop over the rest of the list
     const int grid = min((P.total_tiles + 3) / 4, BAND_GRID);
@@ -616,26 +621,26 @@ static void launch_band_t(const DevPtrs &P, int parity, int full_u, float scale,
     const int xcd = grid == BAND_GRID ? 1 : 0;
     if (P.n_boxes == 1)
         hipLaunchKernelGGL((k_band<ST, C, true>), dim3(grid), dim3(256), 0, s, P, parity, full_u, scale,
-                           1.0f / scale, xcd);
+                           1.0f / scale, xcd, nt);
     else
         hipLaunchKernelGGL((k_band<ST, C, false>), dim3(grid), dim3(256), 0, s, P, parity, full_u, scale,
-                           1.0f / scale, xcd);
+                           1.0f / scale, xcd, nt);
 }
 
 hipError_t launch_band(const DevPtrs &P, int storage, int parity, int full_u, float scale, bool collide,
-                       hipStream_t s) {
+                       int nt, hipStream_t s) {
     if (P.nblk == 0 || P.total_tiles == 0) return hipSuccess;
     if (collide) {
         switch (storage) {
-        case 0: launch_band_t<0, true>(P, parity, full_u, scale, s); break;
-        case 1: launch_band_t<1, true>(P, parity, full_u, scale, s); break;
-        case 2: launch_band_t<2, true>(P, parity, full_u, scale, s); break;
-        default: launch_band_t<3, true>(P, parity, full_u, scale, s); break;
+        case 0: launch_band_t<0, true>(P, parity, full_u, scale, nt, s); break;
+        case 1: launch_band_t<1, true>(P, parity, full_u, scale, nt, s); break;
+        case 2: launch_band_t<2, true>(P, parity, full_u, scale, nt, s); break;
+        default: launch_band_t<3, true>(P, parity, full_u, scale, nt, s); break;
         }
     } else if (storage == 0) {
-        launch_band_t<0, false>(P, parity, full_u, scale, s);
+        launch_band_t<0, false>(P, parity, full_u, scale, 0, s);
     } else {
-        launch_band_t<1, false>(P, parity, full_u, scale, s);
+        launch_band_t<1, false>(P, parity, full_u, scale, 0, s);
     }
     return hipGetLastError();
 }

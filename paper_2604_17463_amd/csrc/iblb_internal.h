@@ -227,7 +227,7 @@ hipError_t launch_node(const DevPtrs &P, bool f64, int mode, int parity, hipStre
 hipError_t launch_bulk(const DevPtrs &P, int storage, int parity, int full_u, float scale,
                        const Launch &L, bool skip_band, hipStream_t s);
 hipError_t launch_band(const DevPtrs &P, int storage, int parity, int full_u, float scale,
-                       bool collide, hipStream_t s);
+                       bool collide, int nt, hipStream_t s);
 hipError_t launch_interp(const DevPtrs &P, bool f64, int mode, double *Uout, hipStream_t s);
 hipError_t launch_epoch(const DevPtrs &P, hipStream_t s);
 hipError_t launch_inside(const DevPtrs &P, bool f64, int slot, hipStream_t s);

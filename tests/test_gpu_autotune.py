@@ -25,8 +25,13 @@ GRAPH, AUTOTUNE = 1, 2
 
 def test_second_init_reuses_the_tuned_launch():
     import paper_2604_17463_amd as P
+    from iblb_inputs.configs import Box, Workload
     say("autotune kept in the process")
-    wl = configs.plain_c1()
+    # a box size no other test tunes, so that the first init here times the
+    # candidates whatever ran before in the process
+    c1 = configs.plain_c1()
+    b0 = c1.boxes[0]
+    wl = Workload("autotune-keep", [Box(b0.nx + 8, b0.ny, b0.nz, tau=b0.tau)], c1.droplets, storage=c1.storage)
     t0 = time.perf_counter()
     a = P.Simulation(wl, storage=1, flags=GRAPH | AUTOTUNE)
     t1 = time.perf_counter()
