@@ -252,6 +252,53 @@ def test_plain_c1_fp32_parity(perm):
     assert abs(drops[0]["height"] - od[0]["height"]) < 1e-5 * od[0]["height"]
 
 
+def _padded_rows_c1(storage):
+    # C1 in a box 30 cells wide: rows padded to 32 cells, little enough that
+    # the stream-collide also writes the row padding (zeros) with the row's
+    # last line, in every storage
+    r = 8.0
+    v, t = mesh.sphere(3, r, (15.0, 16.0, 9.0))
+    return Workload("padded-rows", [Box(30, 32, 24, tau=1.0)],
+                    [Droplet(0, v, t, sigma=0.01, theta_eq=math.radians(90.0), xi=0.05 * r, k_vol=0.0)],
+                    storage=storage)
+
+
+def test_padded_rows_match_oracle(perm):
+    say("padded rows fp64 / fp32, 100 steps")
+    wl = _padded_rows_c1(F64)
+    s, ref = _run_pair(wl, F64, 100)
+    f, u = s.read_state(0, want_u=True)
+    f = to_oracle(f, perm)
+    assert rel_l2(deviation(f), deviation(ref.f[0])) < 1e-10
+    assert rel_l2(u, ref.last_u[0]) < 1e-10
+    assert np.abs(s.read_nodes(0) - ref.q[0]).max() < 1e-10
+    wl = _padded_rows_c1(F32)
+    s, ref = _run_pair(wl, F32, 100)
+    f, u = s.read_state(0, want_u=True)
+    f = to_oracle(f, perm)
+    assert rel_l2(deviation(f), deviation(ref.f[0])) < 1e-4
+    assert rel_l2(u, ref.last_u[0]) < 1e-5
+    assert np.abs(s.read_nodes(0) - ref.q[0]).max() < 1e-5
+
+
+@pytest.mark.parametrize("storage", [F32, F16])
+def test_padded_rows_give_identical_results_across_launches(storage):
+    say("padded rows, launch shapes", storage)
+    wl = _padded_rows_c1(storage)
+    ref = None
+    for launch in ((32, 2, 1, 0, 0), (64, 1, 1, 1, 0), (64, 2, 2, 0, 3), (128, 2, 1, 1, 0, 1)):
+        s = sim(wl, storage, flags=GRAPH)
+        s.set_launch(*launch)
+        s.step(40)
+        got = (s.read_state(0), s.read_nodes(0))
+        s.close()
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got[0], ref[0]), launch
+            assert np.array_equal(got[1], ref[1]), launch
+
+
 @pytest.mark.parametrize("storage", [F32, F16])
 def test_graph_replay_is_bitwise_equal_to_eager(storage):
     say("graph vs eager", storage)
