@@ -54,7 +54,13 @@ thread_local std::string g_last_error = "no error";
 
 constexpr size_t ALIGN = 256;
 constexpr size_t BIG_ALIGN = 2u << 20;
-constexpr int MULTI = 32;         // steps per multi-step graph
+// Steps per multi-step graph.  A run takes the longest that fits at each
+// point.  The first step of a graph cannot overlap its node pass with a bulk
+// kernel: a graph launch waits for the previous graph, whose last bulk
+// kernel is still running.  With the shorter lengths a run of 20 steps
+// replays two graphs instead of twenty single steps.
+constexpr int MULTI_LEN[] = {32, 16, 8, 4, 2};
+constexpr int N_MULTI = (int)(sizeof(MULTI_LEN) / sizeof(MULTI_LEN[0]));
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -417,10 +423,11 @@ struct iblb_ctx {
     DevPtrs P{};
     Launch L{};
     hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][advect first]
-    // MULTI consecutive steps from a pending advection, by starting parity:
-    // one launch instead of MULTI (the host cost of a launch is close to a
-    // step's device time at the sizes of the spreading workload)
-    hipGraphExec_t multi[2] = {nullptr, nullptr};
+    // MULTI_LEN[i] consecutive steps from a pending advection, by starting
+    // parity: one launch instead of MULTI_LEN[i] (the host cost of a launch
+    // is close to a step's device time at the sizes of the spreading
+    // workload)
+    hipGraphExec_t multi[N_MULTI][2] = {};
     bool pending = false;  // advection of the last step not yet applied
     int parity = 0;
     int64_t step = 0;
@@ -598,11 +605,12 @@ iblb_status flush(iblb_ctx *c) {
 }
 
 void drop_graphs(iblb_ctx *c) {
-    for (auto &e : c->multi)
-        if (e) {
-            (void)hipGraphExecDestroy(e);
-            e = nullptr;
-        }
+    for (auto &row : c->multi)
+        for (auto &e : row)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
     for (auto &row : c->exec)
         for (auto &e : row)
             if (e) {
@@ -633,22 +641,23 @@ iblb_status build_graphs(iblb_ctx *c) {
                 return set_err(c, IBLB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         }
     if (c->plan.nblk == 0) return IBLB_OK;  // no advection: single steps only
-    for (int p = 0; p < 2; ++p) {
-        hipGraph_t g = nullptr;
-        HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-        const iblb_status st = enqueue_steps(c, c->capture, p, true, MULTI);
-        hipError_t e = hipStreamEndCapture(c->capture, &g);
-        if (st != IBLB_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return st;
+    for (int li = 0; li < N_MULTI; ++li)
+        for (int p = 0; p < 2; ++p) {
+            hipGraph_t g = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+            const iblb_status st = enqueue_steps(c, c->capture, p, true, MULTI_LEN[li]);
+            hipError_t e = hipStreamEndCapture(c->capture, &g);
+            if (st != IBLB_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess)
+                return set_err(c, IBLB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&c->multi[li][p], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess)
+                return set_err(c, IBLB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         }
-        if (e != hipSuccess)
-            return set_err(c, IBLB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-        e = hipGraphInstantiate(&c->multi[p], g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess)
-            return set_err(c, IBLB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-    }
     return IBLB_OK;
 }
 
@@ -1260,14 +1269,19 @@ iblb_status iblb_step(iblb_ctx *c, int64_t n) {
     for (int64_t k = 0; k < n;) {
         const int a = c->pending ? 1 : 0;
         const int p0 = c->parity;
-        int64_t m = 1;
-        if (a && n - k >= MULTI && c->multi[p0]) {
-            // MULTI steps, each starting with the previous step's advection
-            HIPCHK(c, hipGraphLaunch(c->multi[p0], c->stream));
-            m = MULTI;
-        } else if (c->exec[p0][a]) {
+        int64_t m = 0;
+        for (int li = 0; a && li < N_MULTI && !m; ++li)
+            if (n - k >= MULTI_LEN[li] && c->multi[li][p0]) {
+                // MULTI_LEN[li] steps, each starting with the previous
+                // step's advection
+                HIPCHK(c, hipGraphLaunch(c->multi[li][p0], c->stream));
+                m = MULTI_LEN[li];
+            }
+        if (!m && c->exec[p0][a]) {
             HIPCHK(c, hipGraphLaunch(c->exec[p0][a], c->stream));
-        } else {
+            m = 1;
+        }
+        if (!m) {
             // eager: up to 256 steps as one pipelined run
             m = std::min<int64_t>(n - k, 256);
             iblb_status st = enqueue_steps(c, c->stream, p0, a == 1, (int)m);

@@ -311,6 +311,26 @@ def test_graph_replay_is_bitwise_equal_to_eager(storage):
     assert np.array_equal(a.read_nodes(0), b.read_nodes(0))
 
 
+@pytest.mark.parametrize("after", [0, 1])
+def test_graphs_of_every_length_match_eager_steps(after):
+    # runs of 63, 30, 7 and 2 steps replay the 32-, 16-, 8-, 4- and 2-step
+    # graphs and single steps in both schedules; the eager run takes the same
+    # 103 steps in one call
+    say("graph lengths vs eager, schedule", after)
+    wl = configs.plain_c1()
+    a = sim(wl, F32, flags=0)
+    b = sim(wl, F32, flags=GRAPH)
+    for s in (a, b):
+        s.set_launch(32, 2, 1, 0, 0, after)
+    a.step(103)
+    for n in (1, 63, 30, 7, 2):
+        b.step(n)
+    assert np.array_equal(a.read_state(0), b.read_state(0))
+    assert np.array_equal(a.read_nodes(0), b.read_nodes(0))
+    a.close()
+    b.close()
+
+
 def test_runs_are_deterministic():
     say("determinism")
     wl = configs.plain_c1()
