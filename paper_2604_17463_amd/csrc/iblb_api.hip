@@ -778,6 +778,7 @@ iblb_status autotune(iblb_ctx *c) {
     // 1. block shape, rows per thread, store policy: fastest bulk kernel
     Launch best = c->L;
     double tbest = 1e300;
+    std::vector<std::pair<double, Launch>> tried;
     for (int nt : {0, 1})
         for (int bx : {32, 64, 128, 256}) {
             if (bx > (int)round_up((size_t)nxmax, 32)) continue;
@@ -788,12 +789,30 @@ iblb_status autotune(iblb_ctx *c) {
                     double ms = 0;
                     iblb_status st = timed(L, &ms);
                     if (st != IBLB_OK) return st;
+                    tried.push_back({ms, L});
                     if (ms < tbest) {
                         tbest = ms;
                         best = L;
                     }
                 }
         }
+    // Up to three more block shapes whose bulk kernel alone is within 3 % of
+    // the fastest go on to whole steps too: skipping the band tiles, beside
+    // the band and mesh kernels, the shapes can rank otherwise (at
+    // 256x256x128 in FP32 the bulk kernel alone took 128x1, 128x2 and 256x1
+    // within 1 % of each other, and whole steps 0.294, 0.257 and 0.251 ms).
+    std::stable_sort(tried.begin(), tried.end(),
+                     [](const std::pair<double, Launch> &a, const std::pair<double, Launch> &b) {
+                         return a.first < b.first;
+                     });
+    std::vector<Launch> shapes{best};
+    for (const auto &t : tried) {
+        if (t.first > tbest * 1.03 || shapes.size() >= 4) break;
+        bool seen = false;
+        for (const Launch &h : shapes)
+            seen = seen || (h.bx == t.second.bx && h.by == t.second.by && h.nt == t.second.nt);
+        if (!seen) shapes.push_back(t.second);
+    }
     // 2. with meshes present and the step replayed as graphs, the schedule
     //    and a cap on the bulk grid are judged by whole steps: the workgroups
     //    the cap does not take leave CU slots to the mesh kernels that run
@@ -802,31 +821,36 @@ iblb_status autotune(iblb_ctx *c) {
     //    candidate starts from the initial state.
     if (c->plan.nblk > 0 && (c->plan.flags & IBLB_FLAG_GRAPH)) {
         const int cus = c->P.n_cus;
-        const int wpg = best.bx * best.by / 64;  // waves per workgroup
         double sbest = 1e300;
         Launch chosen = best;
-        for (int after = 0; after < (c->P.contrast ? 1 : 2); ++after)
-            for (int waves_per_cu : {0, 16, 12, 8, 6})
-                for (int cpt : {1, 2}) {
-                    Launch L = best;
-                    L.cpt = cpt;
-                    L.after = after;
-                    if (launch_problem(L)) continue;
-                    L.maxg = waves_per_cu ? std::max(1, cus * waves_per_cu / wpg) : 0;
-                    c->L = L;
-                    iblb_status st = upload_rows(c);
-                    if (st != IBLB_OK) return st;
-                    if (L.maxg && c->L.grid >= c->P.n_rowgroups) continue;  // no cap at this size
-                    double ms = 0;
-                    st = reset_state(c);
-                    if (st == IBLB_OK) st = build_graphs(c);
-                    if (st == IBLB_OK) st = time_steps(c, &ms);
-                    if (st != IBLB_OK) return st;
-                    if (ms < sbest) {
-                        sbest = ms;
-                        chosen = L;
+        for (size_t si = 0; si < shapes.size(); ++si) {
+            const Launch &shape = shapes[si];
+            const int wpg = shape.bx * shape.by / 64;  // waves per workgroup
+            for (int after = 0; after < (c->P.contrast ? 1 : 2); ++after)
+                for (int waves_per_cu : {0, 16, 12, 8, 6})
+                    for (int cpt : {1, 2}) {
+                        // the other shapes: uncapped, at their own rows per thread
+                        if (si > 0 && (waves_per_cu || cpt != shape.cpt)) continue;
+                        Launch L = shape;
+                        L.cpt = cpt;
+                        L.after = after;
+                        if (launch_problem(L)) continue;
+                        L.maxg = waves_per_cu ? std::max(1, cus * waves_per_cu / wpg) : 0;
+                        c->L = L;
+                        iblb_status st = upload_rows(c);
+                        if (st != IBLB_OK) return st;
+                        if (L.maxg && c->L.grid >= c->P.n_rowgroups) continue;  // no cap at this size
+                        double ms = 0;
+                        st = reset_state(c);
+                        if (st == IBLB_OK) st = build_graphs(c);
+                        if (st == IBLB_OK) st = time_steps(c, &ms);
+                        if (st != IBLB_OK) return st;
+                        if (ms < sbest) {
+                            sbest = ms;
+                            chosen = L;
+                        }
                     }
-                }
+        }
         best = chosen;
         iblb_status st = reset_state(c);
         if (st != IBLB_OK) return st;
