@@ -150,6 +150,18 @@ def traffic_record():
     return rec
 
 
+def counted_traffic(rec, workload: str, storage: str, launch):
+    """HBM bytes per bulk launch counted for this workload and storage in
+    this launch shape (threads_x, rows, rows per thread, streaming stores,
+    grid cap), from the record's entry for that shape, or None."""
+    if not rec or rec.get("workload") != workload or rec.get("storage") != storage:
+        return None
+    for e in [rec] + list(rec.get("launches", [])):
+        if tuple(e.get("launch", ()))[:5] == tuple(launch)[:5]:
+            return e["hbm_bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(wl, seconds: float):
     """The oracle on the host cores (all the process may use, then one
     thread), on the same workload from its initial state: steps until
@@ -526,11 +538,7 @@ def main():
     achieved = bytes_k1 / (k1_ms * 1e-3) / 1e9
     launch = sim.get_launch()
     sim.close()
-    tr = traffic_record()
-    traffic = None
-    if (tr and tr.get("workload") == wl.name and tr.get("storage") == args.storage
-            and tuple(tr.get("launch", ()))[:5] == tuple(launch)[:5]):
-        traffic = tr["hbm_bytes_per_launch"]
+    traffic = counted_traffic(traffic_record(), wl.name, args.storage, launch)
     step_bytes = bytes_k1 + band * BYTES_PER_BAND_CELL + nodes * BYTES_PER_NODE
     out = {
         "metric": METRIC, "value": round(mlups, 3), "unit": "MLUPS", "n_gpus": 1,

@@ -8,7 +8,7 @@ By default (or with --bulk NAME=LAUNCH ...) a plain device copy of a known
 size (torch's copy kernel) first serves as the calibration of the memory
 counters; then the bulk stream-collide kernel runs over every cell, 3 +
 `reps` times, on each named workload (spreading, box256, multidroplet,
-batched) in the given launch shape (threads_x, rows, cells_per_thread,
+batched) in the given launch shape (threads_x, rows, rows_per_thread,
 streaming_stores, max_workgroups).
 
 With --steps WORKLOAD N it instead runs N graph-replayed FP32 steps of a
@@ -49,7 +49,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--bulk", nargs="+", default=["spreading=128,1,1,0,1024", "box256=256,1,1,1,0"],
                     metavar="NAME=LAUNCH",
-                    help="workloads and bulk launches (threads_x,rows,cells_per_thread,"
+                    help="workloads and bulk launches (threads_x,rows,rows_per_thread,"
                          "streaming_stores,max_workgroups) for the counter runs")
     ap.add_argument("--steps", nargs=2, metavar=("WORKLOAD", "N"),
                     help="run N steps of spreading, batched or multidroplet instead")
@@ -84,10 +84,12 @@ def main():
         sim.set_launch(*launch)
         sim.time_stream_collide(reps=3)
         ms = sim.time_stream_collide(reps=args.reps)
-        res[name] = {"workload": wl.name, "cells": wl.cells, "bulk_ms": ms,
+        # keyed by the whole NAME=LAUNCH item: one workload may be timed in
+        # several launch shapes
+        res[item] = {"workload": wl.name, "cells": wl.cells, "bulk_ms": ms,
                      "launch": list(sim.get_launch())}
         sim.close()
-        print(json.dumps({name: res[name]}), flush=True)
+        print(json.dumps({item: res[item]}), flush=True)
     print(json.dumps(res), flush=True)
 
 
