@@ -560,6 +560,46 @@ def test_spreading_step_matches_oracle_from_gpu_state(perm):
     assert abs(boxes[0]["mass"] - oracle.mass(ref.f[0])) < 1e-9 * oracle.mass(ref.f[0])
 
 
+# FP16: the oracle starts from the stored state, which it reads exactly; each
+# stored deviation of the new state is the FP32 result rounded to FP16,
+# within 2^-11 of it relatively, so populations are held to 2^-11 + 1e-5
+@pytest.mark.parametrize("storage,tol_f", [(F32, 1e-5), (F16, 5e-4)])
+def test_batched_step_matches_oracle_from_gpu_state(storage, tol_f, perm):
+    # the 64-box batched workload at full size, autotuned as the bench runs
+    # it, after 20 steps: one box in eight (sizes 48 to 128 cells a side, each
+    # with its own droplet, contact angle and tau) advanced one step by the
+    # oracle from the GPU's own populations and nodes; the GPU's next step of
+    # the whole batch must agree in each
+    say("batched one-step parity full size", storage)
+    wl = configs.batched_c4()
+    s = sim(wl, storage, flags=GRAPH | AUTOTUNE)
+    s.step(20)
+    picks = list(range(0, len(wl.boxes), 8))
+    for b in picks:
+        assert wl.droplets[b].box == b
+    f0 = {b: to_oracle(s.read_state(b), perm) for b in picks}
+    q0 = {b: s.read_nodes(b) for b in picks}
+    s.step(1)
+    drops, boxes = s.observables()
+    assert all(bx["status_bits"] == 0 for bx in boxes)
+    for b in picks:
+        d = wl.droplets[b]
+        one = Workload("one", [wl.boxes[b]], [Droplet(0, **{k: getattr(d, k) for k in (
+            "nodes", "tris", "sigma", "theta_eq", "xi", "n_exp", "m_exp", "k_vol")})], storage=F64)
+        ref = oracle.OracleSim(one, f0=[f0[b]])
+        ref.q[0] = q0[b].copy()
+        ref.step(1)
+        assert ref.below_wall == 0
+        f1 = to_oracle(s.read_state(b), perm)
+        err_f = rel_l2(deviation(f1), deviation(ref.f[0]))
+        err_q = np.abs(s.read_nodes(b) - ref.q[0]).max()
+        say(f"box {b} {wl.boxes[b].nx}x{wl.boxes[b].ny}x{wl.boxes[b].nz}: populations {err_f:.3e}, "
+            f"nodes {err_q:.3e} lu")
+        assert err_f < tol_f, (b, err_f)
+        assert err_q < 1e-6, (b, err_q)
+    s.close()
+
+
 @pytest.mark.parametrize("tau_in", [0.0, 1.4])
 def test_timing_the_mesh_chain_leaves_the_run_unchanged(tau_in):
     say("mesh chain timing", tau_in)
