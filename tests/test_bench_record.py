@@ -1,6 +1,6 @@
-"""The bench's reading of the committed counter record (CPU only): the HBM
-bytes it reports as `traffic` come from the record's entry for the launch
-shape the run uses, and from no other workload, storage or shape."""
+"""The bench on the CPU: the HBM bytes it reports as `traffic` come from the
+committed counter record's entry for the launch shape the run uses, and from
+no other workload, storage or shape; and it refuses any GPU count but one."""
 import json
 import os
 import sys
@@ -46,3 +46,13 @@ def test_record_entries_are_consistent():
         assert e["algorithmic_bytes_per_launch"] == alg
         # every population is read and written at least once per launch
         assert 1.0 <= e["hbm_bytes_per_launch"] / alg < 1.05
+
+
+def test_bench_refuses_several_gpus():
+    # one GPU only: any other count exits before touching a device
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
