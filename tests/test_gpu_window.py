@@ -1,7 +1,8 @@
 """Whole-step parity at the 512x512x256 sixteen-droplet size (67 M cells),
 through the C ABI, on windows of the box.
 
-After 20 GPU steps the GPU's own state (populations of each window plus a
+After 20 GPU steps (graph replay, autotuned launch, as the bench runs the
+box) the GPU's own state (populations of each window plus a
 one-cell halo, and every droplet's nodes) is advanced one step by the FP64
 oracle: forces of every droplet (Eqs. 9-11), spreading into the whole box
 (Eq. 8), the stream-collide with the Guo source on the window box (Eqs. 1-6;
@@ -31,7 +32,7 @@ from _helpers import deviation, lib_to_oracle_perm, rel_l2, say, to_oracle
 
 pytestmark = pytest.mark.gpu
 
-F32, F16, GRAPH = 1, 2, 1
+F32, F16, GRAPH, AUTOTUNE = 1, 2, 1, 2
 STEPS = 20
 # (droplet on the 4x4 grid, window lo x/y, window extent x/y)
 WINDOWS = (
@@ -52,7 +53,8 @@ def test_multidroplet_step_on_windows_matches_oracle(storage, scale, tol_f):
     box = wl.boxes[0]
     nx, ny, nz = box.nx, box.ny, box.nz
     perm = lib_to_oracle_perm()
-    s = P.Simulation(wl, storage=storage, flags=GRAPH, dev_scale=scale)
+    # graphs and the autotuned launch, as the bench runs this box
+    s = P.Simulation(wl, storage=storage, flags=GRAPH | AUTOTUNE, dev_scale=scale)
     s.step(STEPS)
     q0 = [s.read_nodes(d) for d in range(len(wl.droplets))]
     halo = []
