@@ -84,6 +84,21 @@ class Workload:
         return replace(self, storage=storage, dev_scale=dev_scale)
 
 
+def workload_hash(wl: Workload) -> str:
+    """sha256 of everything that defines a workload's inputs (box sizes and
+    parameters, meshes, droplet parameters): stored traces carry it, so that
+    a trace is only compared with runs of the inputs it was made from."""
+    import hashlib
+    h = hashlib.sha256()
+    for b in wl.boxes:
+        h.update(repr((b.nx, b.ny, b.nz, b.tau, b.rho0, b.zbc, tuple(b.body_force))).encode())
+    for d in wl.droplets:
+        h.update(np.ascontiguousarray(d.nodes, dtype=np.float64).tobytes())
+        h.update(np.ascontiguousarray(d.tris, dtype=np.int32).tobytes())
+        h.update(repr((d.box, d.sigma, d.theta_eq, d.xi, d.n_exp, d.m_exp, d.k_vol)).encode())
+    return h.hexdigest()
+
+
 def _deg(a: float) -> float:
     return a * math.pi / 180.0
 

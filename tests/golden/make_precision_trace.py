@@ -16,7 +16,7 @@ sys.path.insert(0, HERE)
 
 import oracle  # noqa: E402
 from iblb_inputs import configs  # noqa: E402
-from make_spreading_trace import workload_hash  # noqa: E402
+from iblb_inputs.configs import workload_hash  # noqa: E402
 
 
 def trace(tau, steps, every):

@@ -4,7 +4,6 @@ steps up to 20,000 steps.  Calls only the oracle and the input generators.
 
     python tests/golden/make_spreading_trace.py [steps] [every]
 """
-import hashlib
 import json
 import os
 import sys
@@ -13,21 +12,9 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-import numpy as np  # noqa: E402
-
 import oracle  # noqa: E402
 from iblb_inputs import configs  # noqa: E402
-
-
-def workload_hash(wl):
-    h = hashlib.sha256()
-    for b in wl.boxes:
-        h.update(repr((b.nx, b.ny, b.nz, b.tau, b.rho0, b.zbc, tuple(b.body_force))).encode())
-    for d in wl.droplets:
-        h.update(np.ascontiguousarray(d.nodes, dtype=np.float64).tobytes())
-        h.update(np.ascontiguousarray(d.tris, dtype=np.int32).tobytes())
-        h.update(repr((d.box, d.sigma, d.theta_eq, d.xi, d.n_exp, d.m_exp, d.k_vol)).encode())
-    return h.hexdigest()
+from iblb_inputs.configs import workload_hash  # noqa: E402
 
 
 def main():

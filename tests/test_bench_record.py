@@ -56,3 +56,54 @@ def test_bench_refuses_several_gpus():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def _headline_trace():
+    with open(bench.MTRACE) as fh:
+        return json.load(fh)
+
+
+def test_headline_oracle_trace_is_of_the_headline_workload():
+    # written by tests/golden/make_multidroplet_trace.py (oracle only): the
+    # inputs it was made from are those the bench runs, its rows lie every
+    # 25 steps from step 25 (where the driver's 5 + 20 steps end), and the
+    # closed box keeps its mass to rounding
+    from iblb_inputs import configs
+    tr = _headline_trace()
+    wl = configs.multidroplet_c5()
+    assert tr["workload_sha256"] == configs.workload_hash(wl)
+    steps = [r["step"] for r in tr["rows"]]
+    assert steps == list(range(25, 25 * len(steps) + 1, 25))
+    for r in tr["rows"]:
+        assert abs(r["mass"] - wl.cells) < 1e-9 * wl.cells
+        assert len(r["droplets"]) == len(wl.droplets)
+
+
+class _StandIn:
+    """Reports the stored trace's values at whatever step it has reached."""
+
+    def __init__(self, tr, step):
+        self.rows = {r["step"]: r for r in tr["rows"]}
+        self.now = step
+
+    def step(self, n):
+        self.now += n
+
+    def observables(self):
+        r = self.rows.get(self.now)
+        drops = [dict(d, step=self.now) for d in (r["droplets"] if r else [{}])]
+        return drops, [{"step": self.now, "mass": r["mass"] if r else 0.0}]
+
+
+def test_headline_error_is_taken_at_the_next_trace_row():
+    from iblb_inputs import configs
+    tr = _headline_trace()
+    wl = configs.multidroplet_c5()
+    sim = _StandIn(tr, 20)
+    out = bench.headline_oracle_errors(sim, wl)
+    assert out["step"] == 25 and sim.now == 25
+    assert all(out[k] == 0.0 for k in ("height", "contact_radius", "volume", "area", "mass"))
+    last = tr["rows"][-1]["step"]
+    assert bench.headline_oracle_errors(_StandIn(tr, last + 1), wl) is None
+    other = configs.multidroplet_c5(seed=1)
+    assert bench.headline_oracle_errors(_StandIn(tr, 20), other) is None

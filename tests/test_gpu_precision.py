@@ -51,7 +51,7 @@ PHASE = {"f64": 0, "f32": 2, "f16dev": 2, "bf16dev": 200}
 def test_precision_workload_against_oracle_trace(tau):
     import paper_2604_17463_amd as P
     from iblb_inputs import configs
-    from make_spreading_trace import workload_hash
+    from iblb_inputs.configs import workload_hash
 
     with open(os.path.join(HERE, "golden", f"precision_trace_oracle_tau{tau:g}.json")) as fh:
         tr = json.load(fh)

@@ -33,7 +33,7 @@ TOL = {"height": 1e-4, "contact_radius": 1e-3, "volume": 1e-6, "mass": 1e-8}
 def test_spreading_trace_fp32_matches_the_oracle_every_100_steps():
     import paper_2604_17463_amd as P
     from iblb_inputs import configs
-    from make_spreading_trace import workload_hash
+    from iblb_inputs.configs import workload_hash
 
     with open(os.path.join(HERE, "golden", "spreading_trace_oracle.json")) as fh:
         tr = json.load(fh)
@@ -80,7 +80,7 @@ TOL_LOWP = {
 def test_spreading_trace_reduced_precision_matches_the_oracle(name):
     import paper_2604_17463_amd as P
     from iblb_inputs import configs
-    from make_spreading_trace import workload_hash
+    from iblb_inputs.configs import workload_hash
 
     with open(os.path.join(HERE, "golden", "spreading_trace_oracle.json")) as fh:
         tr = json.load(fh)
