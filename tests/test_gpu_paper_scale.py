@@ -140,3 +140,40 @@ def test_paper_scale_forces_spread_and_step_match_oracle():
     _, boxes = s.observables()
     assert boxes[0]["status_bits"] == 0
     assert abs(boxes[0]["mass"] - oracle.mass(ref.f[0])) < 1e-9 * oracle.mass(ref.f[0])
+
+
+def test_paper_neck_step_matches_oracle_from_gpu_state():
+    # the Sec. 4 sphere released at the wall at its scale (300 x 300 x 250,
+    # R0 = 60, tau = 0.56, the lowest nodes at xi above the wall where the
+    # neck forms): after 300 GPU steps, the oracle's step from the GPU's
+    # populations and nodes against the GPU's next step (deviations 1e-5
+    # relative L2, nodes 1e-6 lu, mass 1e-9)
+    import numpy as np
+
+    import oracle
+    import paper_2604_17463_amd as P
+    from _helpers import deviation, lib_to_oracle_perm, rel_l2, to_oracle
+    say("paper-scale neck run: one step against the oracle")
+    wl = configs.paper_neck()
+    s = P.Simulation(wl, storage=1, flags=1)
+    s.step(300)
+    perm = lib_to_oracle_perm()
+    f0 = to_oracle(s.read_state(0), perm)
+    q0 = s.read_nodes(0)
+    s.step(1)
+    _, boxes = s.observables()
+    assert boxes[0]["status_bits"] == 0
+    f1 = to_oracle(s.read_state(0), perm)
+    q1 = s.read_nodes(0)
+    s.close()
+    ref = oracle.OracleSim(wl, f0=[f0])
+    del f0
+    ref.q[0] = q0.copy()
+    ref.step(1)
+    assert ref.below_wall == 0
+    err_f = rel_l2(deviation(f1), deviation(ref.f[0]))
+    err_q = np.abs(q1 - ref.q[0]).max()
+    say(f"populations {err_f:.3e}, nodes {err_q:.3e} lu")
+    assert err_f < 1e-5, err_f
+    assert err_q < 1e-6, err_q
+    assert abs(boxes[0]["mass"] - oracle.mass(ref.f[0])) < 1e-9 * oracle.mass(ref.f[0])
